@@ -1,0 +1,189 @@
+"""Seeded synthetic read sets (the workloads), shared by the library's benchmark and
+the tests.
+
+This module only draws random DNA: genomes, read positions, strands and
+substitution errors.  It holds none of the graph-construction arithmetic.  Reads are
+returned as one ASCII byte array (``b"ACGT"`` letters) plus ``uint64`` offsets
+(read i is ``bases[offsets[i]:offsets[i+1]]``), the format both the GPU library's
+packer and the CPU oracle consume.
+
+Recipe (every workload): a genome of i.i.d. bases with the given base
+probabilities; read starts uniform on ``[0, G - L]``; each read reverse-complemented
+with probability 0.5; then each base independently substituted with probability
+``err`` by one of the three other bases, uniformly.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ALPHABET = np.frombuffer(b"ACGT", dtype=np.uint8)
+SEED_BASE = 1003_1940 * 10
+
+
+@dataclass
+class ReadSet:
+    bases: np.ndarray     # uint8 ASCII, concatenated reads
+    offsets: np.ndarray   # uint64, n_reads + 1
+    params: dict = field(default_factory=dict)
+
+    @property
+    def n_reads(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def n_bases(self) -> int:
+        return int(self.offsets[-1])
+
+    def kmer_count(self, k: int) -> int:
+        """Number of read positions holding a k-mer: sum over reads of max(0, L - k + 1)."""
+        lens = np.diff(self.offsets.astype(np.int64))
+        return int(np.maximum(lens - k + 1, 0).sum())
+
+    def subset(self, idx) -> "ReadSet":
+        """Reads ``idx`` (an index array) as a new read set."""
+        idx = np.asarray(idx, dtype=np.int64)
+        lens = np.diff(self.offsets.astype(np.int64))[idx]
+        offs = np.zeros(len(idx) + 1, np.uint64)
+        np.cumsum(lens, out=offs[1:])
+        parts = [self.bases[int(self.offsets[i]):int(self.offsets[i + 1])] for i in idx]
+        bases = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+        return ReadSet(bases, offs, dict(self.params, subset=len(idx)))
+
+
+def random_genome(rng: np.random.Generator, size: int, gc: float = 0.5) -> np.ndarray:
+    """i.i.d. base codes 0..3 (A, C, G, T) with P(C) = P(G) = gc / 2."""
+    p = np.array([(1 - gc) / 2, gc / 2, gc / 2, (1 - gc) / 2])
+    return rng.choice(4, size=size, p=p).astype(np.uint8)
+
+
+def insert_repeats(rng: np.random.Generator, genome: np.ndarray, copies: int, length: int) -> None:
+    """Write one random element of ``length`` bases over the genome at ``copies``
+    non-overlapping uniform positions (the genome keeps its size)."""
+    element = rng.integers(0, 4, size=length, dtype=np.uint8)
+    slots = len(genome) // length
+    for s in np.sort(rng.choice(slots, size=copies, replace=False)):
+        genome[s * length:(s + 1) * length] = element
+
+
+def sample_reads(rng: np.random.Generator, genome: np.ndarray, n_reads: int, read_len,
+                 err: float, p_rc: float = 0.5, chunk: int = 1 << 20) -> ReadSet:
+    """Reads of length ``read_len`` (an int, or an array of per-read lengths)."""
+    lens = (np.full(n_reads, int(read_len), np.int64) if np.isscalar(read_len)
+            else np.asarray(read_len, np.int64))
+    offsets = np.zeros(n_reads + 1, np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    out = np.empty(int(offsets[-1]), np.uint8)
+    G = len(genome)
+    for c0 in range(0, n_reads, chunk):
+        c1 = min(n_reads, c0 + chunk)
+        for L in np.unique(lens[c0:c1]):
+            sel = np.nonzero(lens[c0:c1] == L)[0] + c0
+            starts = rng.integers(0, G - L + 1, size=len(sel))
+            codes = genome[starts[:, None] + np.arange(L)[None, :]]
+            flip = rng.random(len(sel)) < p_rc
+            codes[flip] = 3 - codes[flip, ::-1]
+            if err > 0:
+                hit = rng.random(codes.shape) < err
+                codes[hit] = (codes[hit] + rng.integers(1, 4, size=int(hit.sum()),
+                                                         dtype=np.uint8)) & 3
+            rows = offsets[sel].astype(np.int64)
+            out[rows[:, None] + np.arange(L)[None, :]] = ALPHABET[codes]
+    return ReadSet(out, offsets)
+
+
+def from_strings(reads) -> ReadSet:
+    """A read set from a list of Python strings (upper-case ACGT)."""
+    enc = [r.encode() for r in reads]
+    offsets = np.zeros(len(enc) + 1, np.uint64)
+    np.cumsum([len(e) for e in enc], out=offsets[1:])
+    bases = np.frombuffer(b"".join(enc), dtype=np.uint8).copy()
+    return ReadSet(bases, offsets)
+
+
+# ---------------------------------------------------------------------------
+# The benchmark workloads.
+
+def plain_small(scale: float = 1.0) -> ReadSet:
+    """Plain build, k = 31: 100,000-base uniform genome; 10,000 reads of length 100,
+    strand p = 0.5, 1% substitution errors."""
+    rng = np.random.default_rng(SEED_BASE + 0)
+    g = random_genome(rng, 100_000)
+    n = max(1, int(10_000 * scale))
+    rs = sample_reads(rng, g, n, 100, 0.01)
+    rs.params = dict(workload="plain_small_k31", genome=100_000, reads=n, read_len=100,
+                     err=0.01, seed=SEED_BASE + 0)
+    return rs
+
+
+def plain_repeats(scale: float = 1.0) -> ReadSet:
+    """Plain build, k = 31: 5,000,000-base uniform genome carrying 200 exact copies
+    of one random 1,000-base element; 2,000,000 reads of length 100 (40x), strand
+    p = 0.5, 0.5% substitution errors.  ``scale`` shrinks the read count only."""
+    rng = np.random.default_rng(SEED_BASE + 1)
+    g = random_genome(rng, 5_000_000)
+    insert_repeats(rng, g, 200, 1000)
+    n = max(1, int(2_000_000 * scale))
+    rs = sample_reads(rng, g, n, 100, 0.005)
+    rs.params = dict(workload="plain_repeats_k31", genome=5_000_000, repeats="200x1000",
+                     reads=n, read_len=100, err=0.005, seed=SEED_BASE + 1)
+    return rs
+
+
+def plain_large(scale: float = 1.0) -> ReadSet:
+    """Plain build, k = 63: 100,000,000-base genome with GC content 0.41;
+    40,000,000 reads of length 150 (60x), strand p = 0.5, 1% errors.  ``scale``
+    shrinks the genome and the read count together (coverage stays 60x)."""
+    rng = np.random.default_rng(SEED_BASE + 2)
+    G = max(1000, int(100_000_000 * scale))
+    g = random_genome(rng, G, gc=0.41)
+    n = max(1, int(40_000_000 * scale))
+    rs = sample_reads(rng, g, n, 150, 0.01)
+    rs.params = dict(workload="plain_large_k63", genome=G, reads=n, read_len=150, err=0.01,
+                     gc=0.41, seed=SEED_BASE + 2)
+    return rs
+
+
+def batched_sets(n_sets: int = 256, scale: float = 1.0) -> list:
+    """Batched build, k = 31: independent read sets, each from its own genome of
+    size log-uniform in [20,000, 2,000,000]; reads of length 100 at coverage
+    uniform in [10x, 50x], strand p = 0.5, 1% errors."""
+    root = np.random.SeedSequence(SEED_BASE + 3)
+    out = []
+    for child in root.spawn(n_sets):
+        rng = np.random.default_rng(child)
+        G = int(round(math.exp(rng.uniform(math.log(2e4), math.log(2e6)))))
+        cov = rng.uniform(10, 50)
+        g = random_genome(rng, G)
+        n = max(1, int(round(G * cov / 100 * scale)))
+        rs = sample_reads(rng, g, n, 100, 0.01)
+        rs.params = dict(genome=G, coverage=cov, reads=n)
+        out.append(rs)
+    return out
+
+
+def served_trace(n_requests: int, rate: float = 200.0, pool_size: int = 256,
+                 scale: float = 1.0):
+    """Served build: Poisson arrivals (mean ``rate`` per second) of requests whose
+    read sets come from a pool of ``pool_size`` sets: genome size log-uniform in
+    [10,000, 5,000,000], read length 100 or 150, coverage 30x, 1% errors, k drawn
+    from {31, 63}.  Returns (arrival_times_s, pool_index, k_per_request, pool)."""
+    rng = np.random.default_rng(SEED_BASE + 4)
+    pool = []
+    for child in np.random.SeedSequence(SEED_BASE + 40).spawn(pool_size):
+        prng = np.random.default_rng(child)
+        G = int(round(math.exp(prng.uniform(math.log(1e4), math.log(5e6)) + math.log(scale))))
+        G = max(G, 1000)
+        L = int(prng.choice([100, 150]))
+        n = max(1, int(round(G * 30 / L)))
+        rs = sample_reads(prng, random_genome(prng, G), n, L, 0.01)
+        rs.params = dict(genome=G, read_len=L, reads=n)
+        pool.append(rs)
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps)
+    which = rng.integers(0, pool_size, size=n_requests)
+    ks = rng.choice([31, 63], size=n_requests)
+    return arrivals, which, ks, pool
