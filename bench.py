@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the bi-directed de Bruijn graph build on one MI355X.
+
+A step is one full build (edge table and node table) of the 2,000,000-read,
+k = 31 workload (5,000,000-base genome with 200 copies of a 1,000-base repeat,
+reads of length 100, 0.5% substitutions), inputs already packed and resident in
+HBM.  Prints one JSON line: k-mers/s, the roofline of the dominant kernel
+(timed live with per-stage HIP events on the build stream) and the oracle timed
+on a bounded sample of the same reads on the host.
+"""
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator, k, key bytes)
+    "plain_repeats_k31": ("plain_repeats", 31),
+    "plain_small_k31": ("plain_small", 31),
+    "plain_large_k63": ("plain_large", 63),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_names():
+    return ["start", "offsets", "enum_hist", "plan", "enum_scatter", "levels", "local_sort",
+            "rle_count", "rle_write", "end"]
+
+
+def algorithmic_bytes(stage, n_keys, n_unique, n_bases, n_reads, w, row_bytes):
+    """Bytes a kernel must move at minimum (reads of its inputs + writes of its
+    outputs), per launch."""
+    if stage == "enum_hist":
+        return n_bases / 4 + 16 * n_reads
+    if stage == "enum_scatter":
+        return n_bases / 4 + 16 * n_reads + n_keys * w
+    if stage == "local_sort":
+        return 2 * n_keys * w
+    if stage == "rle_write":
+        return n_keys * w + n_unique * (row_bytes + 8)
+    return None
+
+
+def run_cpu_baseline(rs, k, target_s=15.0):
+    """The oracle, as is, on a bounded prefix of the reads (host cores)."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.host_threads(0)
+    n = 2000
+    while True:
+        sub = rs.subset(np.arange(min(n, rs.n_reads)))
+        t0 = time.perf_counter()
+        oracle.build_graph(sub.bases, sub.offsets, k, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= target_s / 4 or n >= rs.n_reads:
+            break
+        n = int(min(rs.n_reads, n * max(2.0, min(8.0, target_s / 2 / max(dt, 1e-3)))))
+    kmers = sub.kmer_count(k)
+    return {"value": kmers / dt, "unit": "k-mers/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sub.n_reads} reads of the workload ({kmers} k-mer positions), "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain_repeats_k31", choices=sorted(WORKLOADS))
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md and not implemented.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1003_1940_amd as dbg
+    from paper_1003_1940_amd import api, synth
+
+    gen_name, k = WORKLOADS[args.workload]
+    log(f"generating {args.workload} (scale {args.scale})")
+    rs = getattr(synth, gen_name)(scale=args.scale)
+    n_reads, n_bases = rs.n_reads, rs.n_bases
+    n_k = rs.kmer_count(k)
+    n_e = rs.kmer_count(k + 1)
+    w = 8 if k <= 31 else 16
+    log(f"{n_reads} reads, {n_bases} bases, {n_k} k-mers, {n_e} (k+1)-mers")
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    packed, offs, _ = api.upload(rs.bases, rs.offsets, dev)
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t0
+    out = api.alloc_outputs(k, n_k, n_k, dev, zkey=True)
+    ws = api.Workspace(n_reads, 1, n_k, k, dev)
+    result = torch.zeros(3, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    lib = api.load()
+    lib.dbg_set_stage_events.restype = ctypes.c_int
+    lib.dbg_set_stage_events.argtypes = [ctypes.c_void_p, ctypes.c_int]
+
+    def step():
+        api.build_async(packed, n_bases, offs, k, n_k, out, n_k, n_k, result, ws, stream)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    n_nodes, n_edges, status = api.read_result(result)
+    if status != 0:
+        raise SystemExit(f"device status {status}: {api.strerror(status)}")
+
+    # per-step stage events (HIP events recorded by the library on `stream`)
+    NE = 20
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE)] for _ in range(args.steps)]
+    for step_ev in ev:  # torch creates the HIP event on first record
+        for e in step_ev:
+            e.record(stream)
+    torch.cuda.synchronize()
+    handles = [(ctypes.c_void_p * NE)(*[e.cuda_event for e in step_ev]) for step_ev in ev]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    start.record(stream)
+    for s in range(args.steps):
+        lib.dbg_set_stage_events(ctypes.cast(handles[s], ctypes.c_void_p), NE)
+        step()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    lib.dbg_set_stage_events(None, 0)
+    total_ms = start.elapsed_time(stop)
+    ms = total_ms / args.steps
+    n_nodes, n_edges, status = api.read_result(result)
+    if status != 0:
+        raise SystemExit(f"device status {status}: {api.strerror(status)}")
+
+    names = stage_names()
+    stages = {}
+    for tbl, base in (("edges", 0), ("nodes", 10)):
+        for i in range(1, 10):
+            vals = [ev[s][base + i - 1].elapsed_time(ev[s][base + i]) for s in range(args.steps)]
+            stages[f"{tbl}.{names[i]}"] = float(np.mean(vals))
+    log("stages (ms): " + ", ".join(f"{k_}={v:.3f}" for k_, v in stages.items()))
+
+    # dominant single-kernel stage and its roofline
+    row_bytes = {"edges": 2 * w + 1 + 4 + w, "nodes": w + 4}
+    uniq = {"edges": n_edges, "nodes": n_nodes}
+    keys = {"edges": n_e, "nodes": n_k}
+    best = None
+    for name, t in stages.items():
+        tbl, st = name.split(".")
+        b = algorithmic_bytes(st, keys[tbl], uniq[tbl], n_bases, n_reads, w, row_bytes[tbl])
+        if b is not None and (best is None or t > best[1]):
+            best = (name, t, b)
+    kname, kms, kbytes = best
+    achieved = kbytes / (kms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "ms": round(kms, 4)}
+
+    # sort + reduce share of the build: partition levels, LDS sort, run-length reduce
+    sr_ms = sum(v for n_, v in stages.items()
+                if n_.split(".")[1] in ("enum_scatter", "levels", "local_sort", "rle_count",
+                                         "rle_write"))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        cpu = run_cpu_baseline(rs, k)
+
+    line = {
+        "metric": "k-mers/s into bi-directed graph",
+        "value": n_k / (ms / 1e3),
+        "unit": "k-mers/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64" if w == 8 else "u128",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "reads": n_reads, "read_len": rs.params.get("read_len"),
+                   "k": k, "genome": rs.params.get("genome"), "kmers": n_k, "kplus1mers": n_e,
+                   "nodes": n_nodes, "edges": n_edges, "scale": args.scale},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_ms": {k_: round(v, 4) for k_, v in stages.items()},
+        "sort_reduce_ms": round(sr_ms, 4),
+        "h2d_upload_and_pack_s": round(h2d_s, 4),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * dbg.h -- C ABI of the MI355X (gfx950) bi-directed de Bruijn graph builder.
+ *
+ * Computes, for a set of DNA reads over {A, C, G, T} and an odd k, the graph of
+ * Kundeti, Rajasekaran, Dinh, Vaughn and Thapar, "Efficient Parallel and Out of
+ * Core Algorithms for Constructing Large Bi-directed de Bruijn Graphs":
+ *   - the node table: every canonical k-mer (Sec. 2: the lexicographically
+ *     smaller of a k-mer and its reverse complement) with the number of read
+ *     positions whose k-mer canonicalises to it (STEP-3 of BiConstruct, Sec. 3,
+ *     with counts);
+ *   - the edge list: for every (k+1)-mer of the reads, the canonical bi-directed
+ *     edge (u, v, o1, o2) of STEP-1 (Sec. 3), deduplicated with multiplicities
+ *     (STEP-2).
+ * Counts are taken over the reads as given (each (k+1)-mer position contributes
+ * 1), not over reads plus reverse complements, which would double every count.
+ *
+ * Encodings
+ *   bases:   A=0 C=1 G=2 T=3; complement = 3 - code.  Lexicographic order A<C<G<T.
+ *   packed:  base j of the concatenated read stream sits in bits
+ *            [63 - 2(j mod 32), 62 - 2(j mod 32)] of 64-bit word j / 32
+ *            (first base most significant).  Read i is bases
+ *            [read_offsets[i], read_offsets[i+1]); reads may start anywhere.
+ *   keys:    a string of L bases is the integer sum c_j 4^(L-1-j), so integer
+ *            order is string order.  k <= 31: node keys and edge keys ((k+1)-mers,
+ *            up to 64 bits at k = 31) are one uint64_t.  33 <= k <= 63: two
+ *            uint64_t per key, low word first (a little-endian 128-bit integer).
+ *   orient:  (o1 << 1) | o2 with '+' (right-pointing head; the k-mer is the
+ *            canonical strand) = 0 and '-' (left-pointing head) = 1.
+ *   an edge (u, v, o1, o2) stands for the (k+1)-mer: strand o1 of u followed by
+ *   the last base of strand o2 of v; read along the other strand the same edge
+ *   is (v, u, not o2, not o1).  u <= v always; when u = v the smaller
+ *   orientation pair of the two readings is reported (this only decides
+ *   homopolymer (k+1)-mers, which the printed table would otherwise give two
+ *   records).
+ *
+ * Output order (deterministic, exactly one correct output exists)
+ *   nodes ascending by k-mer key; edges ascending by the canonical (k+1)-mer they
+ *   stand for (zkey).  Edge records and canonical (k+1)-mers are in one-to-one
+ *   correspondence.
+ *
+ * Ownership and execution
+ *   Every pointer marked "device" is device memory owned by the caller (for
+ *   example allocated through PyTorch).  The library never allocates or frees
+ *   memory and never synchronises: all work is enqueued on `stream`, and results
+ *   (including dbg_result_t) are valid once the caller has synchronised with the
+ *   stream.  Concurrent calls are safe on different streams with distinct
+ *   workspaces and outputs.
+ *
+ * Errors
+ *   Arguments checked on the host return a non-zero dbg_status and enqueue
+ *   nothing.  Conditions only visible to the device (malformed offsets, more
+ *   keys than max_keys, output capacity too small) are written to
+ *   dbg_result_t.status (first error wins); after a device-side error the
+ *   remaining kernels return early and the outputs are undefined, except for
+ *   DBG_E_CAPACITY, where the first `capacity` rows are valid and n_nodes /
+ *   n_edges hold the true counts.
+ */
+#ifndef DBG_H
+#define DBG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DBG_OK = 0,
+  DBG_E_NULL = 1,       /* a required pointer is null */
+  DBG_E_K = 2,          /* k is even, < 1 or > 63 (Sec. 2 requires odd k) */
+  DBG_E_OFFSETS = 3,    /* offsets not monotone, offsets[0] != 0 or offsets[n] != n_bases */
+  DBG_E_OVERFLOW = 4,   /* more keys than max_keys, or max_keys >= 2^32 */
+  DBG_E_CAPACITY = 5,   /* more distinct nodes or edges than the output capacity */
+  DBG_E_WORKSPACE = 6,  /* workspace smaller than dbg_workspace_bytes() */
+  DBG_E_HIP = 7,        /* a HIP launch failed */
+  DBG_E_BASE = 8,       /* a byte other than A, C, G, T (either case) */
+  DBG_E_ARG = 9,        /* other invalid argument (e.g. n_sets == 0) */
+  DBG_E_INTERNAL = 10   /* internal list capacity exceeded (a bug) */
+} dbg_status;
+
+/* Node table outputs (device).  kmer: capacity rows of one uint64_t (k <= 31) or
+ * two (k >= 33).  count: capacity uint32_t. */
+typedef struct {
+  void *kmer;
+  uint32_t *count;
+  uint64_t capacity;
+} dbg_nodes_t;
+
+/* Edge list outputs (device).  u, v: capacity rows, same width as node keys.
+ * orient: capacity bytes.  mult: capacity uint32_t.  zkey: optional (NULL to
+ * skip), capacity rows of the canonical (k+1)-mer, one uint64_t (k <= 31) or two
+ * (k >= 33). */
+typedef struct {
+  void *u;
+  void *v;
+  uint8_t *orient;
+  uint32_t *mult;
+  void *zkey;
+  uint64_t capacity;
+} dbg_edges_t;
+
+/* Device-resident result record, written at the end of a build. */
+typedef struct {
+  uint64_t n_nodes; /* distinct canonical k-mers (true count, even beyond capacity) */
+  uint64_t n_edges; /* distinct canonical edges */
+  uint32_t status;  /* DBG_OK or the first device-side error */
+  uint32_t reserved;
+} dbg_result_t;
+
+/* Bytes of device workspace a build needs.  n_reads, n_sets as passed to the
+ * build; max_keys is an upper bound on the number of k-mer positions
+ * (sum over reads of max(0, L - k + 1)); n_bases is always a valid bound.
+ * Returns 0 for invalid k. */
+size_t dbg_workspace_bytes(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k);
+
+/* Build the graph of one read set (Sec. 3, BiConstruct STEP-1 to STEP-3).
+ *   packed        device, ceil(n_bases / 32) words (layout above)
+ *   n_bases       bases in the stream (= read_offsets[n_reads])
+ *   read_offsets  device, n_reads + 1 base offsets, read_offsets[0] = 0
+ *   max_keys      bound used for the workspace (see dbg_workspace_bytes), < 2^32
+ *   nodes, edges  host structs holding device output pointers and capacities;
+ *                 full output needs capacity >= the distinct count (always
+ *                 enough: capacity >= max_keys)
+ *   result        device dbg_result_t
+ *   workspace     device, >= dbg_workspace_bytes(n_reads, 1, max_keys, k) bytes,
+ *                 256-byte aligned; its contents are clobbered. */
+int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+              uint64_t n_reads, int k, uint64_t max_keys, const dbg_nodes_t *nodes,
+              const dbg_edges_t *edges, dbg_result_t *result, void *workspace,
+              size_t workspace_bytes, hipStream_t stream);
+
+/* Build the graphs of n_sets independent read sets in one launch sequence.  Set s
+ * is reads [set_read_offsets[s], set_read_offsets[s+1]) of the same stream
+ * (device array, n_sets + 1 entries, first 0, last n_reads).  Outputs are the
+ * per-set tables concatenated in set order; node_set_offsets / edge_set_offsets
+ * (device, n_sets + 1 entries each) receive where each set's rows begin.  Each
+ * set's rows are exactly what dbg_build gives for that set alone. */
+int dbg_build_batched(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                      uint64_t n_reads, const uint64_t *set_read_offsets, uint64_t n_sets,
+                      int k, uint64_t max_keys, const dbg_nodes_t *nodes,
+                      const dbg_edges_t *edges, uint64_t *node_set_offsets,
+                      uint64_t *edge_set_offsets, dbg_result_t *result, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+
+/* Pack ASCII bases (device, n_bases bytes of A/C/G/T, either case) into the
+ * 2-bit stream (device, ceil(n_bases / 32) words; bits past the last base are 0).
+ * A byte outside {A,C,G,T,a,c,g,t} sets result->status = DBG_E_BASE (result is
+ * device memory; its other fields are untouched). */
+int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
+                   dbg_result_t *result, hipStream_t stream);
+
+/* Profiling aid.  When `events` is non-null, every later build records
+ * events[i] (hipEvent_t handles created by the caller) on its stream at fixed
+ * stage boundaries, DBG_STAGE_EVENTS per build: for the edge table (base 0)
+ * and then the node table (base 10),
+ *   base+0 table start            base+5 after the remaining partition levels
+ *   base+1 after key offsets      base+6 after the LDS bucket sort (one kernel)
+ *   base+2 after the enumeration  base+7 after run counting
+ *          histogram (one kernel) base+8 after the run-length write (one kernel)
+ *   base+3 after bucket planning  base+9 table end
+ *   base+4 after the enumeration scatter (one kernel)
+ * n_events must be >= DBG_STAGE_EVENTS.  Process-wide setting, meant for
+ * single-stream benchmarking; pass NULL to stop recording. */
+#define DBG_STAGE_EVENTS 20
+int dbg_set_stage_events(hipEvent_t *events, int n_events);
+
+/* Static description of a status code. */
+const char *dbg_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBG_H */

@@ -1,0 +1,286 @@
+"""Python binding of ``libdbg.so``: argument marshalling only.
+
+Every step of the construction runs in the library's HIP kernels; PyTorch only
+provides device memory and streams.  There is no CPU fallback: if the library
+is missing or no GPU is present these functions raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdbg.so")
+
+DBG_OK, DBG_E_CAPACITY = 0, 5
+_STATUS_NAMES = {0: "DBG_OK", 1: "DBG_E_NULL", 2: "DBG_E_K", 3: "DBG_E_OFFSETS",
+                 4: "DBG_E_OVERFLOW", 5: "DBG_E_CAPACITY", 6: "DBG_E_WORKSPACE", 7: "DBG_E_HIP",
+                 8: "DBG_E_BASE", 9: "DBG_E_ARG", 10: "DBG_E_INTERNAL"}
+
+
+class DbgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {_STATUS_NAMES.get(code, code)} ({strerror(code)})")
+
+
+class _Nodes(ctypes.Structure):
+    _fields_ = [("kmer", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("capacity", ctypes.c_uint64)]
+
+
+class _Edges(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("orient", ctypes.c_void_p),
+                ("mult", ctypes.c_void_p), ("zkey", ctypes.c_void_p),
+                ("capacity", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libdbg.so (built by ``paper_1003_1940_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1003_1940_amd.hipbuild.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        u64, i32, vp, sz = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+        lib.dbg_workspace_bytes.restype = sz
+        lib.dbg_workspace_bytes.argtypes = [u64, u64, u64, i32]
+        lib.dbg_build.restype = i32
+        lib.dbg_build.argtypes = [vp, u64, vp, u64, i32, u64, ctypes.POINTER(_Nodes),
+                                  ctypes.POINTER(_Edges), vp, vp, sz, vp]
+        lib.dbg_build_batched.restype = i32
+        lib.dbg_build_batched.argtypes = [vp, u64, vp, u64, vp, u64, i32, u64,
+                                          ctypes.POINTER(_Nodes), ctypes.POINTER(_Edges), vp, vp,
+                                          vp, vp, sz, vp]
+        lib.dbg_pack_ascii.restype = i32
+        lib.dbg_pack_ascii.argtypes = [vp, u64, vp, vp, vp]
+        lib.dbg_strerror.restype = ctypes.c_char_p
+        lib.dbg_strerror.argtypes = [i32]
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().dbg_strerror(code).decode()
+
+
+def workspace_bytes(n_reads: int, n_sets: int, max_keys: int, k: int) -> int:
+    return int(load().dbg_workspace_bytes(n_reads, n_sets, max_keys, k))
+
+
+def key_words(k: int) -> int:
+    """uint64 words per key: 1 for k <= 31, 2 for k >= 33."""
+    return 1 if k <= 31 else 2
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t, name, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+
+
+def pack(ascii_bases: torch.Tensor, stream=None):
+    """ASCII bases (uint8 device tensor) -> 2-bit packed words (int64 device tensor
+    holding the uint64 bit patterns) and a device result record whose status
+    turns DBG_E_BASE on a byte outside ACGT/acgt."""
+    _check_dev(ascii_bases, "ascii_bases", torch.uint8)
+    n = ascii_bases.numel()
+    packed = torch.empty(max(1, (n + 31) // 32), dtype=torch.int64, device=ascii_bases.device)
+    res = torch.zeros(3, dtype=torch.int64, device=ascii_bases.device)
+    rc = load().dbg_pack_ascii(_ptr(ascii_bases), n, _ptr(packed), _ptr(res), _stream(stream))
+    if rc:
+        raise DbgError(rc, "dbg_pack_ascii")
+    return packed, res
+
+
+@dataclass
+class Graph:
+    """Device-resident result.  Keys are int64 tensors holding uint64 bit
+    patterns: shape (n,) for k <= 31, (n, 2) as (lo, hi) for k >= 33."""
+    k: int
+    node_kmer: torch.Tensor
+    node_count: torch.Tensor
+    edge_u: torch.Tensor
+    edge_v: torch.Tensor
+    edge_orient: torch.Tensor
+    edge_mult: torch.Tensor
+    edge_zkey: torch.Tensor | None
+    n_nodes: int = 0
+    n_edges: int = 0
+    status: int = 0
+    node_set_offsets: torch.Tensor | None = None
+    edge_set_offsets: torch.Tensor | None = None
+    extra: dict = field(default_factory=dict)
+
+    def to_numpy(self):
+        """Host copy with keys as (n, 2) uint64 (lo, hi) arrays."""
+        def keys(t, n):
+            a = t[:n].cpu().numpy().view(np.uint64)
+            if a.ndim == 1:
+                a = np.stack([a, np.zeros_like(a)], axis=1)
+            return a
+        nn_, ne = min(self.n_nodes, self.node_count.numel()), min(self.n_edges,
+                                                                  self.edge_mult.numel())
+        return dict(
+            node_key=keys(self.node_kmer, nn_),
+            node_count=self.node_count[:nn_].cpu().numpy().view(np.uint32).astype(np.uint64),
+            edge_u=keys(self.edge_u, ne), edge_v=keys(self.edge_v, ne),
+            edge_orient=self.edge_orient[:ne].cpu().numpy(),
+            edge_mult=self.edge_mult[:ne].cpu().numpy().view(np.uint32).astype(np.uint64),
+            edge_z=keys(self.edge_zkey, ne) if self.edge_zkey is not None else None)
+
+
+class Workspace:
+    """A reusable device workspace (a byte tensor) sized for a bound."""
+
+    def __init__(self, n_reads: int, n_sets: int, max_keys: int, k: int, device="cuda"):
+        self.nbytes = workspace_bytes(n_reads, n_sets, max_keys, k)
+        if self.nbytes == 0:
+            raise DbgError(2, "dbg_workspace_bytes")
+        # 256-byte alignment: torch's caching allocator aligns blocks to 512 bytes
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        assert self.buf.data_ptr() % 256 == 0
+        self.bound = (n_reads, n_sets, max_keys, k)
+
+
+def alloc_outputs(k: int, node_cap: int, edge_cap: int, device="cuda", zkey: bool = True):
+    w = key_words(k)
+    shape = (lambda n: (n,)) if w == 1 else (lambda n: (n, 2))
+    o = dict(
+        node_kmer=torch.empty(shape(max(node_cap, 1)), dtype=torch.int64, device=device),
+        node_count=torch.empty(max(node_cap, 1), dtype=torch.int32, device=device),
+        edge_u=torch.empty(shape(max(edge_cap, 1)), dtype=torch.int64, device=device),
+        edge_v=torch.empty(shape(max(edge_cap, 1)), dtype=torch.int64, device=device),
+        edge_orient=torch.empty(max(edge_cap, 1), dtype=torch.uint8, device=device),
+        edge_mult=torch.empty(max(edge_cap, 1), dtype=torch.int32, device=device),
+        edge_zkey=torch.empty(shape(max(edge_cap, 1)), dtype=torch.int64, device=device)
+        if zkey else None)
+    return o
+
+
+def _structs(out, node_cap, edge_cap):
+    nodes = _Nodes(out["node_kmer"].data_ptr(), out["node_count"].data_ptr(), node_cap)
+    edges = _Edges(out["edge_u"].data_ptr(), out["edge_v"].data_ptr(),
+                   out["edge_orient"].data_ptr(), out["edge_mult"].data_ptr(),
+                   out["edge_zkey"].data_ptr() if out["edge_zkey"] is not None else None, edge_cap)
+    return nodes, edges
+
+
+def build_async(packed, n_bases: int, offsets, k: int, max_keys: int, out: dict,
+                node_cap: int, edge_cap: int, result, workspace: Workspace, stream=None,
+                set_offsets=None, node_set_offsets=None, edge_set_offsets=None):
+    """Enqueue one build (plain, or batched when ``set_offsets`` is given) on the
+    stream without synchronising.  All tensors must be resident on the device."""
+    _check_dev(packed, "packed", torch.int64)
+    _check_dev(offsets, "offsets", torch.int64)
+    _check_dev(result, "result", torch.int64)
+    n_reads = offsets.numel() - 1
+    nodes, edges = _structs(out, node_cap, edge_cap)
+    lib = load()
+    if set_offsets is None:
+        rc = lib.dbg_build(_ptr(packed), n_bases, _ptr(offsets), n_reads, k, max_keys,
+                           ctypes.byref(nodes), ctypes.byref(edges), _ptr(result),
+                           _ptr(workspace.buf), workspace.nbytes, _stream(stream))
+        where = "dbg_build"
+    else:
+        _check_dev(set_offsets, "set_offsets", torch.int64)
+        rc = lib.dbg_build_batched(_ptr(packed), n_bases, _ptr(offsets), n_reads,
+                                   _ptr(set_offsets), set_offsets.numel() - 1, k, max_keys,
+                                   ctypes.byref(nodes), ctypes.byref(edges),
+                                   _ptr(node_set_offsets), _ptr(edge_set_offsets), _ptr(result),
+                                   _ptr(workspace.buf), workspace.nbytes, _stream(stream))
+        where = "dbg_build_batched"
+    if rc:
+        raise DbgError(rc, where)
+
+
+def read_result(result) -> tuple:
+    """(n_nodes, n_edges, status) from a device result record (synchronises)."""
+    r = result.cpu().numpy().view(np.uint64)
+    return int(r[0]), int(r[1]), int(r[2] & 0xFFFFFFFF)
+
+
+def upload(bases: np.ndarray, offsets: np.ndarray, device="cuda", stream=None):
+    """ASCII reads (host) -> (packed words, device offsets, n_bases); packing runs
+    on the device."""
+    n_bases = int(offsets[-1])
+    ascii_d = torch.from_numpy(np.ascontiguousarray(bases[:n_bases], np.uint8)).to(device)
+    if ascii_d.numel() == 0:
+        ascii_d = torch.zeros(1, dtype=torch.uint8, device=device)[:0]
+    packed, res = pack(ascii_d, stream) if n_bases else (
+        torch.zeros(1, dtype=torch.int64, device=device), None)
+    offs = torch.from_numpy(np.ascontiguousarray(offsets, np.uint64).view(np.int64)).to(device)
+    if res is not None:
+        _, _, st = read_result(res)
+        if st:
+            raise DbgError(st, "dbg_pack_ascii")
+    return packed, offs, n_bases
+
+
+def build(bases: np.ndarray, offsets: np.ndarray, k: int, zkey: bool = True, device="cuda",
+          node_cap: int | None = None, edge_cap: int | None = None) -> Graph:
+    """Convenience: upload host reads, build, synchronise, return the device graph
+    sliced to its true sizes."""
+    offsets = np.asarray(offsets, np.uint64)
+    lens = np.diff(offsets.astype(np.int64))
+    n_k = int(np.maximum(lens - k + 1, 0).sum()) if len(lens) else 0
+    packed, offs, n_bases = upload(bases, offsets, device)
+    node_cap = n_k if node_cap is None else node_cap
+    edge_cap = n_k if edge_cap is None else edge_cap
+    out = alloc_outputs(k, node_cap, edge_cap, device, zkey)
+    ws = Workspace(len(offsets) - 1, 1, n_k, k, device)
+    result = torch.zeros(3, dtype=torch.int64, device=device)
+    build_async(packed, n_bases, offs, k, n_k, out, node_cap, edge_cap, result, ws)
+    n_nodes, n_edges, status = read_result(result)
+    if status not in (DBG_OK, DBG_E_CAPACITY):
+        raise DbgError(status, "dbg_build (device)")
+    g = Graph(k, out["node_kmer"], out["node_count"], out["edge_u"], out["edge_v"],
+              out["edge_orient"], out["edge_mult"], out["edge_zkey"], n_nodes, n_edges, status)
+    return g
+
+
+def build_batched(bases: np.ndarray, offsets: np.ndarray, set_read_offsets: np.ndarray, k: int,
+                  zkey: bool = True, device="cuda") -> Graph:
+    """Convenience: several read sets (set s = reads [set_read_offsets[s],
+    set_read_offsets[s+1])) built in one launch sequence; outputs concatenated
+    per set with row offsets in node_set_offsets / edge_set_offsets."""
+    offsets = np.asarray(offsets, np.uint64)
+    sro = np.asarray(set_read_offsets, np.uint64)
+    lens = np.diff(offsets.astype(np.int64))
+    n_k = int(np.maximum(lens - k + 1, 0).sum()) if len(lens) else 0
+    packed, offs, n_bases = upload(bases, offsets, device)
+    out = alloc_outputs(k, n_k, n_k, device, zkey)
+    n_sets = len(sro) - 1
+    ws = Workspace(len(offsets) - 1, n_sets, n_k, k, device)
+    result = torch.zeros(3, dtype=torch.int64, device=device)
+    sets_d = torch.from_numpy(sro.view(np.int64).copy()).to(device)
+    nso = torch.zeros(n_sets + 1, dtype=torch.int64, device=device)
+    eso = torch.zeros(n_sets + 1, dtype=torch.int64, device=device)
+    build_async(packed, n_bases, offs, k, n_k, out, n_k, n_k, result, ws, set_offsets=sets_d,
+                node_set_offsets=nso, edge_set_offsets=eso)
+    n_nodes, n_edges, status = read_result(result)
+    if status not in (DBG_OK, DBG_E_CAPACITY):
+        raise DbgError(status, "dbg_build_batched (device)")
+    return Graph(k, out["node_kmer"], out["node_count"], out["edge_u"], out["edge_v"],
+                 out["edge_orient"], out["edge_mult"], out["edge_zkey"], n_nodes, n_edges, status,
+                 node_set_offsets=nso, edge_set_offsets=eso)

@@ -1,0 +1,166 @@
+// C ABI of the graph builder: argument checks, workspace layout and dispatch on
+// the key width (64-bit keys for k <= 31, 128-bit keys for 33 <= k <= 63).
+#include "dbg_internal.h"
+
+namespace dbg {
+
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) {
+  Layout L{};
+  L.key_bytes = k <= 31 ? 8 : 16;
+  const uint64_t cap = k <= 31 ? local_cap<uint64_t>() : local_cap<unsigned __int128>();
+  const int edge_bits = 2 * (k + 1);
+  const uint64_t levels = (uint64_t)((edge_bits + 7) / 8);  // digit levels incl. level 0
+  L.max_tiles = (max_keys + TILE - 1) / TILE + n_sets;
+  L.item_cap = max_keys / cap + 2;
+  // batches per level <= 2 * keys / cap + parents + oversized children
+  L.batch_cap = levels * (2 * (max_keys / cap) + 1) + n_sets + 3 * levels * L.item_cap + 64;
+  L.rle_tiles = (max_keys + TILE - 1) / TILE;
+  if (L.rle_tiles == 0) L.rle_tiles = 1;
+  L.read_blocks = n_reads / ((uint64_t)256 * 16) + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.ctl = take(sizeof(Ctl));
+  L.set_read_off = take(2 * sizeof(uint64_t));
+  L.rbase = take((n_reads + 1) * sizeof(uint64_t));
+  L.block_sums = take(L.read_blocks * sizeof(uint64_t));
+  L.set_kbase = take((n_sets + 1) * sizeof(uint64_t));
+  L.set_tbase = take((n_sets + 1) * sizeof(uint64_t));
+  L.tile_read = take(L.max_tiles * sizeof(uint64_t));
+  L.tile_set = take(L.max_tiles * sizeof(uint32_t));
+  L.hist0 = take(n_sets * 256 * sizeof(uint64_t));
+  L.cursor0 = take(n_sets * 256 * sizeof(uint64_t));
+  for (int i = 0; i < 2; ++i) L.items[i] = take(L.item_cap * sizeof(Item));
+  for (int i = 0; i < 2; ++i) L.hist[i] = take(L.item_cap * 256 * sizeof(uint64_t));
+  L.cursor = take(L.item_cap * 256 * sizeof(uint64_t));
+  L.batches = take(L.batch_cap * sizeof(Batch));
+  L.uniform = take(L.item_cap * sizeof(Item));
+  L.rle_heads = take(L.rle_tiles * sizeof(uint64_t));
+  L.set_uoff = 0;
+  // key buffers: the second one also holds the run starts (max_keys + 1 words)
+  for (int i = 0; i < 2; ++i) L.keys[i] = take((max_keys + 2) * (size_t)L.key_bytes);
+  L.total = off;
+  return L;
+}
+
+static int check_common(uint64_t n_bases, const uint64_t *packed, const uint64_t *read_offsets,
+                        int k, uint64_t max_keys, const dbg_nodes_t *nodes,
+                        const dbg_edges_t *edges, dbg_result_t *result, void *workspace) {
+  if (!read_offsets || !nodes || !edges || !result || !workspace) return DBG_E_NULL;
+  if (n_bases && !packed) return DBG_E_NULL;
+  if (k < 1 || k > 63 || (k & 1) == 0) return DBG_E_K;
+  if (max_keys >= (1ull << 32)) return DBG_E_OVERFLOW;
+  if (nodes->capacity && (!nodes->kmer || !nodes->count)) return DBG_E_NULL;
+  if (edges->capacity && (!edges->u || !edges->v || !edges->orient || !edges->mult))
+    return DBG_E_NULL;
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return DBG_E_WORKSPACE;
+  return DBG_OK;
+}
+
+static int run(const BuildArgs &a, size_t workspace_bytes) {
+  const Layout L = make_layout(a.n_reads, a.n_sets, a.max_keys, a.k);
+  if (workspace_bytes < L.total) return DBG_E_WORKSPACE;
+  const hipError_t e = a.k <= 31 ? run_build_u64(a, L) : run_build_u128(a, L);
+  return e == hipSuccess ? DBG_OK : DBG_E_HIP;
+}
+
+}  // namespace dbg
+
+extern "C" {
+
+size_t dbg_workspace_bytes(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) {
+  if (k < 1 || k > 63 || (k & 1) == 0 || n_sets == 0) return 0;
+  return dbg::make_layout(n_reads, n_sets, max_keys, k).total;
+}
+
+int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+              uint64_t n_reads, int k, uint64_t max_keys, const dbg_nodes_t *nodes,
+              const dbg_edges_t *edges, dbg_result_t *result, void *workspace,
+              size_t workspace_bytes, hipStream_t stream) {
+  const int c = dbg::check_common(n_bases, packed, read_offsets, k, max_keys, nodes, edges, result,
+                                  workspace);
+  if (c != DBG_OK) return c;
+  dbg::BuildArgs a{};
+  a.packed = packed;
+  a.n_bases = n_bases;
+  a.read_offsets = read_offsets;
+  a.n_reads = n_reads;
+  a.set_read_offsets = nullptr;
+  a.n_sets = 1;
+  a.max_keys = max_keys;
+  a.k = k;
+  a.nodes = *nodes;
+  a.edges = *edges;
+  a.result = result;
+  a.workspace = workspace;
+  a.stream = stream;
+  return dbg::run(a, workspace_bytes);
+}
+
+int dbg_build_batched(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                      uint64_t n_reads, const uint64_t *set_read_offsets, uint64_t n_sets,
+                      int k, uint64_t max_keys, const dbg_nodes_t *nodes,
+                      const dbg_edges_t *edges, uint64_t *node_set_offsets,
+                      uint64_t *edge_set_offsets, dbg_result_t *result, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream) {
+  const int c = dbg::check_common(n_bases, packed, read_offsets, k, max_keys, nodes, edges, result,
+                                  workspace);
+  if (c != DBG_OK) return c;
+  if (!set_read_offsets) return DBG_E_NULL;
+  if (n_sets == 0 || n_sets >= (1ull << 31)) return DBG_E_ARG;
+  dbg::BuildArgs a{};
+  a.packed = packed;
+  a.n_bases = n_bases;
+  a.read_offsets = read_offsets;
+  a.n_reads = n_reads;
+  a.set_read_offsets = set_read_offsets;
+  a.n_sets = n_sets;
+  a.max_keys = max_keys;
+  a.k = k;
+  a.nodes = *nodes;
+  a.edges = *edges;
+  a.node_set_offsets = node_set_offsets;
+  a.edge_set_offsets = edge_set_offsets;
+  a.result = result;
+  a.workspace = workspace;
+  a.stream = stream;
+  return dbg::run(a, workspace_bytes);
+}
+
+int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
+                   dbg_result_t *result, hipStream_t stream) {
+  if (n_bases && (!ascii || !packed)) return DBG_E_NULL;
+  if (!result) return DBG_E_NULL;
+  return dbg::launch_pack(ascii, n_bases, packed, result, stream) == hipSuccess ? DBG_OK
+                                                                                : DBG_E_HIP;
+}
+
+int dbg_set_stage_events(hipEvent_t *events, int n_events) {
+  if (events && n_events < DBG_STAGE_EVENTS) return DBG_E_ARG;
+  dbg::set_stage_events(events);
+  return DBG_OK;
+}
+
+const char *dbg_strerror(int status) {
+  switch (status) {
+    case DBG_OK: return "ok";
+    case DBG_E_NULL: return "a required pointer is null";
+    case DBG_E_K: return "k must be odd and in [1, 63]";
+    case DBG_E_OFFSETS: return "read or set offsets are not monotone or do not match n_bases";
+    case DBG_E_OVERFLOW: return "more keys than max_keys, or max_keys >= 2^32";
+    case DBG_E_CAPACITY: return "output capacity below the number of distinct rows";
+    case DBG_E_WORKSPACE: return "workspace too small or not 256-byte aligned";
+    case DBG_E_HIP: return "HIP launch failure";
+    case DBG_E_BASE: return "input byte is not one of A, C, G, T";
+    case DBG_E_ARG: return "invalid argument";
+    case DBG_E_INTERNAL: return "internal list capacity exceeded";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

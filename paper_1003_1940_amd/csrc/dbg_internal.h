@@ -1,0 +1,92 @@
+// Internal layout shared by the kernels and the host-side launch sequence.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/dbg.h"
+
+namespace dbg {
+
+// Streaming kernels (enumeration, partition, run-length reduce): 256 threads x
+// 16 keys = one 4096-key tile per workgroup.
+constexpr int STREAM_NT = 256;
+constexpr int STREAM_KPT = 16;
+constexpr uint64_t TILE = (uint64_t)STREAM_NT * STREAM_KPT;
+
+// LDS-resident bucket sort: 1024 threads (16 waves); a batch of consecutive small
+// buckets of up to LOCAL_CAP keys is sorted entirely in LDS.
+constexpr int LOCAL_NT = 1024;
+constexpr int LOCAL_NW = LOCAL_NT / 64;
+template <typename K> struct LocalCfg;
+template <> struct LocalCfg<uint64_t> { static constexpr int KPT = 16; };
+template <> struct LocalCfg<unsigned __int128> { static constexpr int KPT = 8; };
+template <typename K> constexpr uint64_t local_cap() { return (uint64_t)LOCAL_NT * LocalCfg<K>::KPT; }
+
+// Most-significant-digit levels: level 0 is the enumeration scatter; a key of b
+// bits has ceil(b / 8) digits.
+constexpr int MAX_LEVELS = 16;
+
+struct Ctl {
+  uint32_t status;  // first error found on the device (dbg_status), 0 if none
+  uint32_t pad0;
+  uint64_t n_keys;          // keys of the table being built
+  uint64_t n_tiles;         // enumeration tiles of that table
+  uint64_t items[2];        // oversized buckets waiting for the next level (two lists)
+  uint64_t level_tiles[2];  // 4096-key tiles over each list's buckets
+  uint64_t n_batches;       // batches of small buckets for the LDS sort
+  uint64_t n_uniform;       // oversized buckets whose digits are exhausted (all keys equal)
+  uint64_t n_unique;        // distinct keys of the table
+  uint64_t n_edges, n_nodes;
+  uint32_t capacity_short;  // an output table had more rows than its capacity
+  uint32_t pad1;
+};
+
+struct Item {  // an oversized bucket: keys [off, off + size) of buffer `src`
+  uint64_t off, size, tbase;
+  uint32_t src, pad;
+};
+
+struct Batch {  // consecutive small buckets [off, off + size) of buffer `src`
+  uint64_t off;
+  uint32_t size, src;
+};
+
+// Byte layout of a caller-provided workspace.
+struct Layout {
+  size_t ctl, set_read_off, rbase, block_sums, set_kbase, set_tbase, tile_read, tile_set;
+  size_t hist0, cursor0, items[2], hist[2], cursor, batches, uniform, rle_heads, set_uoff;
+  size_t keys[2];
+  size_t total;
+  uint64_t max_tiles, item_cap, batch_cap, rle_tiles, read_blocks;
+  int key_bytes;
+};
+
+Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k);
+
+struct BuildArgs {
+  const uint64_t *packed;
+  uint64_t n_bases;
+  const uint64_t *read_offsets;
+  uint64_t n_reads;
+  const uint64_t *set_read_offsets;  // null: one set
+  uint64_t n_sets;
+  uint64_t max_keys;
+  int k;
+  dbg_nodes_t nodes;
+  dbg_edges_t edges;
+  uint64_t *node_set_offsets;  // optional, n_sets + 1
+  uint64_t *edge_set_offsets;  // optional
+  dbg_result_t *result;
+  void *workspace;
+  hipStream_t stream;
+};
+
+hipError_t run_build_u64(const BuildArgs &a, const Layout &L);
+hipError_t run_build_u128(const BuildArgs &a, const Layout &L);
+void set_stage_events(hipEvent_t *events);
+hipError_t launch_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
+                       dbg_result_t *result, hipStream_t stream);
+
+}  // namespace dbg

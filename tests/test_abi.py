@@ -1,0 +1,77 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects bad arguments on the host before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dbg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dbg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1003_1940_amd import api
+    return api.load()
+
+
+def test_header_declares_entry_points():
+    assert declared_functions() == ["dbg_build", "dbg_build_batched", "dbg_pack_ascii",
+                                    "dbg_set_stage_events", "dbg_strerror", "dbg_workspace_bytes"]
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror(lib):
+    from paper_1003_1940_amd import api
+    assert api.strerror(0) == "ok"
+    assert "odd" in api.strerror(2)
+
+
+def test_workspace_bytes(lib):
+    from paper_1003_1940_amd import api
+    assert api.workspace_bytes(10, 1, 1000, 31) > 0
+    assert api.workspace_bytes(10, 1, 1000, 30) == 0   # even k
+    assert api.workspace_bytes(10, 1, 1000, 65) == 0
+    assert api.workspace_bytes(10, 0, 1000, 31) == 0   # no sets
+    a = api.workspace_bytes(10, 1, 1000, 31)
+    b = api.workspace_bytes(10, 1, 1000, 33)          # 128-bit keys
+    assert b > a
+    # 2M reads, 140M k-mer positions at k=31 fits in a few GB
+    assert api.workspace_bytes(2_000_000, 1, 140_000_000, 31) < 4e9
+
+
+def _call_build(lib, k=31, max_keys=100, ws_bytes=None, nodes_null=False, result_null=False,
+                offsets_null=False):
+    from paper_1003_1940_amd import api
+    nodes = api._Nodes(0 if nodes_null else 16, 16, 10)
+    edges = api._Edges(16, 16, 16, 16, None, 10)
+    ws = ctypes.c_void_p(256)
+    nbytes = api.workspace_bytes(1, 1, max_keys, 31) if ws_bytes is None else ws_bytes
+    return lib.dbg_build(ctypes.c_void_p(16), 40, None if offsets_null else ctypes.c_void_p(16),
+                         1, k, max_keys, ctypes.byref(nodes), ctypes.byref(edges),
+                         None if result_null else ctypes.c_void_p(16), ws, nbytes, None)
+
+
+def test_host_rejects_bad_arguments(lib):
+    # Every case below is refused before any device work (dummy pointers are
+    # never dereferenced).
+    assert _call_build(lib, k=30) == 2         # DBG_E_K: even k
+    assert _call_build(lib, k=0) == 2
+    assert _call_build(lib, k=65) == 2
+    assert _call_build(lib, nodes_null=True) == 1   # DBG_E_NULL
+    assert _call_build(lib, result_null=True) == 1
+    assert _call_build(lib, offsets_null=True) == 1
+    assert _call_build(lib, max_keys=1 << 32) == 4  # DBG_E_OVERFLOW: counts are 32-bit
+    assert _call_build(lib, ws_bytes=100) == 6      # DBG_E_WORKSPACE
