@@ -33,7 +33,8 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) 
   L.set_tbase = take((n_sets + 1) * sizeof(uint64_t));
   L.tile_read = take(L.max_tiles * sizeof(uint64_t));
   L.tile_set = take(L.max_tiles * sizeof(uint32_t));
-  L.hist0 = take(n_sets * 256 * sizeof(uint64_t));
+  L.thist = take((L.max_tiles + 1) * 256 * sizeof(uint32_t));
+  L.csum = take(((L.max_tiles + 63) / 64 + 1) * 256 * sizeof(uint32_t));
   L.cursor0 = take(n_sets * 256 * sizeof(uint64_t));
   for (int i = 0; i < 2; ++i) L.items[i] = take(L.item_cap * sizeof(Item));
   for (int i = 0; i < 2; ++i) L.hist[i] = take(L.item_cap * 256 * sizeof(uint64_t));
@@ -41,8 +42,9 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) 
   L.batches = take(L.batch_cap * sizeof(Batch));
   L.uniform = take(L.item_cap * sizeof(Item));
   L.rle_heads = take(L.rle_tiles * sizeof(uint64_t));
+  L.bits = take(L.rle_tiles * (TILE / 8));
   L.set_uoff = 0;
-  // key buffers: the second one also holds the run starts (max_keys + 1 words)
+  // key buffers: after the bucket sort buffer 0 holds distinct keys, buffer 1 their counts
   for (int i = 0; i < 2; ++i) L.keys[i] = take((max_keys + 2) * (size_t)L.key_bytes);
   L.total = off;
   return L;

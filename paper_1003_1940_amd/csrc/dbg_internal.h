@@ -15,14 +15,24 @@ constexpr int STREAM_NT = 256;
 constexpr int STREAM_KPT = 16;
 constexpr uint64_t TILE = (uint64_t)STREAM_NT * STREAM_KPT;
 
-// LDS-resident bucket sort: 1024 threads (16 waves); a batch of consecutive small
-// buckets of up to LOCAL_CAP keys is sorted entirely in LDS.
-constexpr int LOCAL_NT = 1024;
-constexpr int LOCAL_NW = LOCAL_NT / 64;
+// LDS-resident bucket sort: a workgroup of NT threads sorts a batch of
+// consecutive small buckets of up to CAP keys entirely in LDS (see
+// k_local_sort): duplicates are merged in an LDS hash table of SLOTS slots, the
+// distinct keys are sorted, and the runs are expanded again.
 template <typename K> struct LocalCfg;
-template <> struct LocalCfg<uint64_t> { static constexpr int KPT = 16; };
-template <> struct LocalCfg<unsigned __int128> { static constexpr int KPT = 8; };
-template <typename K> constexpr uint64_t local_cap() { return (uint64_t)LOCAL_NT * LocalCfg<K>::KPT; }
+template <> struct LocalCfg<uint64_t> {
+  static constexpr int NT = 512;
+  static constexpr int CAP = 6144;
+  static constexpr int SLOTS = 9216;
+  static constexpr int SMALL = 16;  // segments sorted by one lane's network
+};
+template <> struct LocalCfg<unsigned __int128> {
+  static constexpr int NT = 512;
+  static constexpr int CAP = 3072;
+  static constexpr int SLOTS = 4608;
+  static constexpr int SMALL = 16;
+};
+template <typename K> constexpr uint64_t local_cap() { return (uint64_t)LocalCfg<K>::CAP; }
 
 // Most-significant-digit levels: level 0 is the enumeration scatter; a key of b
 // bits has ceil(b / 8) digits.
@@ -56,7 +66,7 @@ struct Batch {  // consecutive small buckets [off, off + size) of buffer `src`
 // Byte layout of a caller-provided workspace.
 struct Layout {
   size_t ctl, set_read_off, rbase, block_sums, set_kbase, set_tbase, tile_read, tile_set;
-  size_t hist0, cursor0, items[2], hist[2], cursor, batches, uniform, rle_heads, set_uoff;
+  size_t thist, csum, cursor0, items[2], hist[2], cursor, batches, uniform, rle_heads, bits, set_uoff;
   size_t keys[2];
   size_t total;
   uint64_t max_tiles, item_cap, batch_cap, rle_tiles, read_blocks;

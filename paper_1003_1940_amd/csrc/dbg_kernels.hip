@@ -248,20 +248,97 @@ __device__ __forceinline__ TileRange enum_tile(const EnumArgs &a, uint64_t t) {
   return r;
 }
 
+// Word and read-base accessors: the tile's span of the packed stream and of
+// rbase is staged in LDS when it fits, otherwise read from global memory.
+constexpr uint64_t ENUM_WCAP = 1024;  // packed words staged per tile
+constexpr uint64_t ENUM_RCAP = 512;   // read bases staged per tile
+
+struct EnumLds {
+  uint64_t words[ENUM_WCAP];
+  uint64_t rb[ENUM_RCAP];
+};
+
+struct TileSrc {
+  const uint64_t *lw;  // LDS words [lw_base, lw_base + lw_n)
+  uint64_t lw_base, lw_n;
+  const uint64_t *gw;
+  uint64_t n_words;
+  const uint64_t *lr;  // LDS read bases [lr_base, lr_base + lr_n)
+  uint64_t lr_base, lr_n;
+  const uint64_t *gr;
+  __device__ __forceinline__ uint64_t word(uint64_t i) const {
+    const uint64_t r = i - lw_base;
+    if (r < lw_n) return lw[r];
+    return i < n_words ? gw[i] : 0ull;
+  }
+  __device__ __forceinline__ uint64_t rbase(uint64_t i) const {
+    const uint64_t r = i - lr_base;
+    return r < lr_n ? lr[r] : gr[i];
+  }
+};
+
+// Stage a tile's words and read bases (whole workgroup; contains a barrier).
+__device__ __forceinline__ TileSrc stage_tile(const EnumArgs &a, const TileRange &tr,
+                                              EnumLds &L) {
+  TileSrc ts;
+  ts.gw = a.packed;
+  ts.n_words = a.n_words;
+  ts.gr = a.rbase;
+  ts.lw = L.words;
+  ts.lr = L.rb;
+  const uint64_t wb = a.offsets[tr.read_lo] >> 5;
+  const uint64_t we = (a.offsets[tr.read_hi] + 31) >> 5;
+  ts.lw_base = wb;
+  ts.lw_n = we - wb <= ENUM_WCAP ? we - wb : 0;
+  ts.lr_base = tr.read_lo;
+  const uint64_t nr = tr.read_hi - tr.read_lo + 1;
+  ts.lr_n = nr <= ENUM_RCAP ? nr : 0;
+  for (uint64_t i = threadIdx.x; i < ts.lw_n; i += blockDim.x)
+    L.words[i] = wb + i < a.n_words ? a.packed[wb + i] : 0ull;
+  for (uint64_t i = threadIdx.x; i < ts.lr_n; i += blockDim.x) L.rb[i] = a.rbase[tr.read_lo + i];
+  __syncthreads();
+  return ts;
+}
+
+__device__ __forceinline__ uint64_t extract_key(const TileSrc &ts, uint64_t p, int len, uint64_t) {
+  const uint64_t wi = p >> 5;
+  const int o = (int)(p & 31) * 2;
+  const uint64_t w0 = ts.word(wi);
+  const uint64_t w1 = ts.word(wi + 1);
+  const uint64_t v = o ? ((w0 << o) | (w1 >> (64 - o))) : w0;
+  return len == 32 ? v : (v >> (64 - 2 * len));
+}
+__device__ __forceinline__ u128 extract_key(const TileSrc &ts, uint64_t p, int len, u128) {
+  const uint64_t wi = p >> 5;
+  const int o = (int)(p & 31) * 2;
+  const uint64_t w0 = ts.word(wi), w1 = ts.word(wi + 1), w2 = ts.word(wi + 2);
+  const uint64_t hi = o ? ((w0 << o) | (w1 >> (64 - o))) : w0;
+  const uint64_t lo = o ? ((w1 << o) | (w2 >> (64 - o))) : w1;
+  return shr<u128>(((u128)hi << 64) | (u128)lo, 128 - 2 * len);
+}
+
 // Keys g0, g0+1, ... (< g_end, at most KPT) into out[]: the canonical key at each
 // position, rolling the forward and reverse-complement registers by one base
 // within a read and re-seeding them at each read start.  Returns the count.
 template <typename K, int KPT>
-__device__ __forceinline__ int enum_keys(const EnumArgs &a, uint64_t g0, uint64_t g_end,
-                                         uint64_t read_lo, uint64_t read_hi, K (&out)[KPT]) {
+__device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, uint64_t g0,
+                                         uint64_t g_end, uint64_t read_lo, uint64_t read_hi,
+                                         K (&out)[KPT]) {
   if (g0 >= g_end) return 0;
-  uint64_t i = upper_bound(a.rbase, read_lo, read_hi + 1, g0) - 1;  // rbase[i] <= g0 < rbase[i+1]
-  uint64_t next = a.rbase[i + 1];
-  uint64_t p = a.offsets[i] + (g0 - a.rbase[i]);
+  // read i with rbase[i] <= g0 < rbase[i+1]
+  uint64_t lo = read_lo, hi = read_hi;  // rbase[lo] <= g0 < rbase[hi]
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (ts.rbase(mid) <= g0) lo = mid;
+    else hi = mid;
+  }
+  uint64_t i = lo;
+  uint64_t next = ts.rbase(i + 1);
+  uint64_t p = a.offsets[i] + (g0 - ts.rbase(i));
   const int len = a.len;
   const K mask = low_mask<K>(2 * len);
   const int top = 2 * len - 2;
-  K fw = extract_bases(a.packed, a.n_words, p, len, K());
+  K fw = extract_key(ts, p, len, K());
   K rc = revcomp(fw, len);
   int n = 0;
   uint64_t g = g0;
@@ -272,13 +349,14 @@ __device__ __forceinline__ int enum_keys(const EnumArgs &a, uint64_t g0, uint64_
         if (g == next) {
           do {
             ++i;
-            next = a.rbase[i + 1];
+            next = ts.rbase(i + 1);
           } while (next == g);
           p = a.offsets[i];
-          fw = extract_bases(a.packed, a.n_words, p, len, K());
+          fw = extract_key(ts, p, len, K());
           rc = revcomp(fw, len);
         } else {
-          const uint32_t c = base_at(a.packed, p + len);
+          const uint64_t q = p + len;
+          const uint32_t c = (uint32_t)(ts.word(q >> 5) >> (62 - 2 * (int)(q & 31))) & 3u;
           fw = ((fw << 2) | (K)c) & mask;
           rc = (rc >> 2) | ((K)(3u - c) << top);
           ++p;
@@ -293,25 +371,103 @@ __device__ __forceinline__ int enum_keys(const EnumArgs &a, uint64_t g0, uint64_
 }
 
 template <typename K>
-__global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint64_t *hist0,
+__global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint32_t *thist,
                                                          const Ctl *ctl) {
   __shared__ uint32_t h[256];
+  __shared__ EnumLds L;
   const uint64_t t = blockIdx.x;
   if (ctl->status || t >= ctl->n_tiles) return;
   h[threadIdx.x] = 0;
-  __syncthreads();
   const TileRange tr = enum_tile(a, t);
+  const TileSrc ts = stage_tile(a, tr, L);
   K keys[STREAM_KPT];
-  const int n = enum_keys<K, STREAM_KPT>(a, tr.start + threadIdx.x * (uint64_t)STREAM_KPT, tr.end,
-                                         tr.read_lo, tr.read_hi, keys);
+  const int n = enum_keys<K, STREAM_KPT>(a, ts, tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
+                                         tr.end, tr.read_lo, tr.read_hi, keys);
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r)
     if (r < n) atomicAdd(&h[msd_digit(keys[r], a.bits, 0)], 1u);
   __syncthreads();
-  const uint32_t c = h[threadIdx.x];
-  if (c)
-    atomicAdd((unsigned long long *)&hist0[(uint64_t)tr.set * 256 + threadIdx.x],
-              (unsigned long long)c);
+  thist[t * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// Column-wise exclusive prefix of the per-tile histograms over all tiles:
+// thist[t][d] becomes the number of keys with digit d in tiles before t, and row
+// n_tiles receives the totals.  Three steps: chunk sums, a scan of the chunk
+// sums (one workgroup, one thread per digit), and the in-chunk prefixes.
+constexpr uint64_t COL_CHUNK = 128;
+constexpr int COL_BATCH = 16;  // independent loads in flight per thread
+
+__global__ __launch_bounds__(256) void k_col_reduce(const uint32_t *thist, uint32_t *csum,
+                                                    const Ctl *ctl) {
+  if (ctl->status) return;
+  const uint64_t nt = ctl->n_tiles;
+  const uint64_t t0 = blockIdx.x * COL_CHUNK;
+  if (t0 >= nt) return;
+  const uint64_t t1 = t0 + COL_CHUNK < nt ? t0 + COL_CHUNK : nt;
+  uint32_t sum = 0;
+  for (uint64_t t = t0; t < t1; t += COL_BATCH) {
+    uint32_t v[COL_BATCH];
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i) v[i] = t + i < t1 ? thist[(t + i) * 256 + threadIdx.x] : 0u;
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i) sum += v[i];
+  }
+  csum[blockIdx.x * 256 + threadIdx.x] = sum;
+}
+
+// One workgroup of 1024 threads: column d = tid % 256 is scanned in four parts.
+__global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const Ctl *ctl) {
+  __shared__ uint32_t part[4][256];
+  if (ctl->status) return;
+  const uint64_t nc = (ctl->n_tiles + COL_CHUNK - 1) / COL_CHUNK;
+  const uint32_t d = threadIdx.x & 255, pi = threadIdx.x >> 8;
+  const uint64_t q = (nc + 3) / 4;
+  const uint64_t c0 = pi * q, c1 = c0 + q < nc ? c0 + q : nc;
+  uint32_t sum = 0;
+  for (uint64_t c = c0; c < c1; c += COL_BATCH) {
+    uint32_t v[COL_BATCH];
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i) v[i] = c + i < c1 ? csum[(c + i) * 256 + d] : 0u;
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i) sum += v[i];
+  }
+  part[pi][d] = sum;
+  __syncthreads();
+  uint32_t run = 0;
+  for (uint32_t i = 0; i < pi; ++i) run += part[i][d];
+  for (uint64_t c = c0; c < c1; c += COL_BATCH) {
+    uint32_t v[COL_BATCH];
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i) v[i] = c + i < c1 ? csum[(c + i) * 256 + d] : 0u;
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i)
+      if (c + i < c1) {
+        csum[(c + i) * 256 + d] = run;
+        run += v[i];
+      }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_col_apply(uint32_t *thist, const uint32_t *csum,
+                                                   const Ctl *ctl) {
+  if (ctl->status) return;
+  const uint64_t nt = ctl->n_tiles;
+  const uint64_t t0 = blockIdx.x * COL_CHUNK;
+  if (t0 >= nt && !(t0 == 0 && nt == 0)) return;
+  const uint64_t t1 = t0 + COL_CHUNK < nt ? t0 + COL_CHUNK : nt;
+  uint32_t run = nt ? csum[blockIdx.x * 256 + threadIdx.x] : 0u;
+  for (uint64_t t = t0; t < t1; t += COL_BATCH) {
+    uint32_t v[COL_BATCH];
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i) v[i] = t + i < t1 ? thist[(t + i) * 256 + threadIdx.x] : 0u;
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; ++i)
+      if (t + i < t1) {
+        thist[(t + i) * 256 + threadIdx.x] = run;
+        run += v[i];
+      }
+  }
+  if (t1 == nt) thist[nt * 256 + threadIdx.x] = run;
 }
 
 // LDS-staged partition of one tile of keys (held in registers) by the digit
@@ -330,8 +486,10 @@ struct PartLds {
 
 template <typename K>
 __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT], int n, int bits,
-                                               int level, uint64_t *cursor, K *dst,
-                                               PartLds<K> &s) {
+                                               int level, uint64_t *cursor, uint64_t my_base,
+                                               K *dst, PartLds<K> &s) {
+  // cursor != null: reserve each digit's range with one atomic on cursor[d];
+  // otherwise thread d already holds its digit's destination start in my_base.
   const uint32_t tid = threadIdx.x;
   uint32_t dig[STREAM_KPT];
 #pragma unroll
@@ -345,8 +503,12 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT], int 
   const uint64_t c = s.cnt[tid];
   uint64_t m;
   const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &m);
-  s.gbase[tid] =
-      c ? (uint64_t)atomicAdd((unsigned long long *)&cursor[tid], (unsigned long long)c) - ex : 0;
+  if (cursor)
+    s.gbase[tid] =
+        c ? (uint64_t)atomicAdd((unsigned long long *)&cursor[tid], (unsigned long long)c) - ex
+          : 0;
+  else
+    s.gbase[tid] = my_base - ex;
   s.cnt[tid] = (uint32_t)ex;
   __syncthreads();
 #pragma unroll
@@ -360,25 +522,37 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT], int 
   __syncthreads();
 }
 
+// Second enumeration pass: keys go to cursor0[set][d] plus the number of keys
+// with digit d in the set's earlier tiles (from the tile prefix), so no atomics.
 template <typename K>
-__global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, uint64_t *cursor0, K *dst,
+__global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const uint64_t *cursor0,
+                                                            const uint32_t *tpre, K *dst,
                                                             const Ctl *ctl) {
   __shared__ PartLds<K> s;
+  __shared__ EnumLds L;
   const uint64_t t = blockIdx.x;
   if (ctl->status || t >= ctl->n_tiles) return;
   const TileRange tr = enum_tile(a, t);
+  const TileSrc ts = stage_tile(a, tr, L);
   K keys[STREAM_KPT];
-  const int n = enum_keys<K, STREAM_KPT>(a, tr.start + threadIdx.x * (uint64_t)STREAM_KPT, tr.end,
-                                         tr.read_lo, tr.read_hi, keys);
-  partition_tile<K>(keys, n, a.bits, 0, cursor0 + (uint64_t)tr.set * 256, dst, s);
+  const int n = enum_keys<K, STREAM_KPT>(a, ts, tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
+                                         tr.end, tr.read_lo, tr.read_hi, keys);
+  const uint64_t t_first = a.set_tbase[tr.set];
+  const uint32_t d = threadIdx.x;
+  const uint64_t base = cursor0[(uint64_t)tr.set * 256 + d] + tpre[t * 256 + d] -
+                        tpre[t_first * 256 + d];
+  partition_tile<K>(keys, n, a.bits, 0, nullptr, base, dst, s);
 }
 
 // ---------------------------------------------------------------------------
 // Bucket planning: after a parent's 256 sub-buckets are counted, scan the counts
-// into cursors and sort each sub-bucket into one of three lists: small ones are
-// grouped (consecutive, up to the LDS capacity) into batches for the LDS sort;
-// oversized ones go to the next partition level, or, when no digit is left (all
-// their keys are equal), to the uniform list.
+// into cursors and put each sub-bucket on one of three lists.  Oversized ones
+// (more keys than the LDS sort holds) go to the next partition level, or, when
+// no digit is left (all their keys are equal), to the uniform list.  Medium
+// ones (more than half the capacity) are a batch each.  Small ones are grouped:
+// consecutive small sub-buckets whose last keys fall in the same window of
+// half the capacity form one batch, so a batch never exceeds the capacity.
+// All 256 sub-buckets are classified in parallel, one per thread.
 
 struct PlanArgs {
   Item *next_items;       // list receiving oversized buckets
@@ -394,60 +568,74 @@ struct PlanArgs {
   int bits;
 };
 
-// Called by the whole workgroup (256 threads): counts[d] of the parent whose keys
-// start at `off`; children live in buffer `src`; `child_level` is the digit level
+struct PlanLds {
+  uint64_t wsum[STREAM_NT / 64 + 1];
+  uint64_t bend[256];
+  uint64_t base[3];
+  uint8_t cls[256];
+  uint32_t win[256];
+};
+
+enum : uint8_t { C_EMPTY = 0, C_SMALL = 1, C_MEDIUM = 2, C_LARGE = 3 };
+
+// Called by the whole workgroup (256 threads), thread d passing the count c of
+// sub-bucket d of the parent whose keys start at `off`; children live in buffer `src`; `child_level` is the digit level
 // that would split a child.
-__device__ void plan_children(const PlanArgs &p, const uint64_t *counts, uint64_t off,
-                              uint32_t src, int child_level, uint64_t *cursor,
-                              uint64_t *s_start, uint64_t *wsum) {
-  const uint32_t tid = threadIdx.x;
-  const uint64_t c = counts[tid];
+__device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint32_t src,
+                              int child_level, uint64_t *cursor, PlanLds &s) {
+  const uint32_t d = threadIdx.x;
   uint64_t total;
-  const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, wsum, &total);
-  cursor[tid] = off + ex;
-  s_start[tid] = ex;
+  const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &total);
+  cursor[d] = off + ex;
+  const uint64_t half = p.local_cap / 2;
+  const uint8_t cls = c == 0 ? C_EMPTY : c <= half ? C_SMALL : c <= p.local_cap ? C_MEDIUM : C_LARGE;
+  const uint32_t win = c ? (uint32_t)((ex + c - 1) / half) : 0u;
+  s.cls[d] = cls;
+  s.win[d] = win;
+  s.bend[d] = 0;
   __syncthreads();
-  if (tid == 0) {
-    const bool digits_left = p.bits - 8 * child_level > 0;
-    uint64_t b_off = 0, b_size = 0;
-    for (int d = 0; d < 256; ++d) {
-      const uint64_t sz = counts[d];
-      if (sz == 0) continue;
-      const uint64_t o = off + s_start[d];
-      if (sz > p.local_cap) {
-        if (b_size) {
-          const uint64_t bi = atomicAdd((unsigned long long *)&p.ctl->n_batches, 1ull);
-          if (bi < p.batch_cap) p.batches[bi] = Batch{b_off, (uint32_t)b_size, src};
-          else set_status(p.ctl, DBG_E_INTERNAL);
-          b_size = 0;
-        }
-        if (digits_left) {
-          const uint64_t ii = atomicAdd((unsigned long long *)p.next_count, 1ull);
-          if (ii < p.item_cap) {
-            p.next_items[ii] = Item{o, sz, 0, src, 0};
-            for (int j = 0; j < 256; ++j) p.next_hist[ii * 256 + j] = 0;
-          } else {
-            set_status(p.ctl, DBG_E_INTERNAL);
-          }
-        } else {
-          const uint64_t ui = atomicAdd((unsigned long long *)&p.ctl->n_uniform, 1ull);
-          if (ui < p.uniform_cap) p.uniform[ui] = Item{o, sz, 0, src, 0};
-          else set_status(p.ctl, DBG_E_INTERNAL);
-        }
+  // batch starts: a medium child, or a small child whose nearest non-empty
+  // predecessor is not small or ends in another window
+  bool start = cls == C_MEDIUM;
+  if (cls == C_SMALL) {
+    int q = (int)d - 1;
+    while (q >= 0 && s.cls[q] == C_EMPTY) --q;
+    start = q < 0 || s.cls[q] != C_SMALL || s.win[q] != win;
+  }
+  const bool large = cls == C_LARGE;
+  const bool digits_left = p.bits - 8 * child_level > 0;
+  uint64_t n_start, n_large;
+  const uint64_t bid_ex = block_exclusive_scan<STREAM_NT>((uint64_t)start, s.wsum, &n_start);
+  const uint64_t lid = block_exclusive_scan<STREAM_NT>((uint64_t)large, s.wsum, &n_large);
+  if (d == 0) {
+    s.base[0] = n_start ? atomicAdd((unsigned long long *)&p.ctl->n_batches, n_start) : 0;
+    s.base[1] = n_large && digits_left
+                    ? atomicAdd((unsigned long long *)p.next_count, n_large) : 0;
+    s.base[2] = n_large && !digits_left
+                    ? atomicAdd((unsigned long long *)&p.ctl->n_uniform, n_large) : 0;
+  }
+  // batch of a small child = the last start at or before it
+  const uint32_t my_batch = (uint32_t)(bid_ex + (start ? 1 : 0)) - 1u;
+  if (cls == C_SMALL || cls == C_MEDIUM)
+    atomicMax((unsigned long long *)&s.bend[my_batch], (unsigned long long)(ex + c));
+  __syncthreads();
+  if (start) {
+    const uint64_t bi = s.base[0] + bid_ex;
+    if (bi < p.batch_cap) p.batches[bi] = Batch{off + ex, (uint32_t)(s.bend[bid_ex] - ex), src};
+    else set_status(p.ctl, DBG_E_INTERNAL);
+  }
+  if (large) {
+    if (digits_left) {
+      const uint64_t ii = s.base[1] + lid;
+      if (ii < p.item_cap) {
+        p.next_items[ii] = Item{off + ex, c, 0, src, 0};
+        for (int j = 0; j < 256; ++j) p.next_hist[ii * 256 + j] = 0;
       } else {
-        if (b_size + sz > p.local_cap) {
-          const uint64_t bi = atomicAdd((unsigned long long *)&p.ctl->n_batches, 1ull);
-          if (bi < p.batch_cap) p.batches[bi] = Batch{b_off, (uint32_t)b_size, src};
-          else set_status(p.ctl, DBG_E_INTERNAL);
-          b_size = 0;
-        }
-        if (b_size == 0) b_off = o;
-        b_size += sz;
+        set_status(p.ctl, DBG_E_INTERNAL);
       }
-    }
-    if (b_size) {
-      const uint64_t bi = atomicAdd((unsigned long long *)&p.ctl->n_batches, 1ull);
-      if (bi < p.batch_cap) p.batches[bi] = Batch{b_off, (uint32_t)b_size, src};
+    } else {
+      const uint64_t ui = s.base[2] + lid;
+      if (ui < p.uniform_cap) p.uniform[ui] = Item{off + ex, c, 0, src, 0};
       else set_status(p.ctl, DBG_E_INTERNAL);
     }
   }
@@ -455,15 +643,18 @@ __device__ void plan_children(const PlanArgs &p, const uint64_t *counts, uint64_
 }
 
 // One workgroup per read set: plan the children of the level-0 partition.
-__global__ __launch_bounds__(STREAM_NT) void k_set_plan(PlanArgs p, const uint64_t *hist0,
+__global__ __launch_bounds__(STREAM_NT) void k_set_plan(PlanArgs p, const uint32_t *tpre,
+                                                        const uint64_t *set_tbase,
                                                         uint64_t *cursor0,
                                                         const uint64_t *set_kbase,
                                                         uint64_t n_sets) {
-  __shared__ uint64_t s_start[256];
-  __shared__ uint64_t wsum[STREAM_NT / 64 + 1];
+  __shared__ PlanLds lds;
   if (p.ctl->status) return;
-  for (uint64_t s = blockIdx.x; s < n_sets; s += gridDim.x)
-    plan_children(p, hist0 + s * 256, set_kbase[s], 0, 1, cursor0 + s * 256, s_start, wsum);
+  const uint32_t d = threadIdx.x;
+  for (uint64_t s = blockIdx.x; s < n_sets; s += gridDim.x) {
+    const uint64_t c = (uint64_t)tpre[set_tbase[s + 1] * 256 + d] - tpre[set_tbase[s] * 256 + d];
+    plan_children(p, c, set_kbase[s], 0, 1, cursor0 + s * 256, lds);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -553,14 +744,13 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K 
 }
 
 __global__ __launch_bounds__(STREAM_NT) void k_level_plan(PlanArgs p, LevelArgs a) {
-  __shared__ uint64_t s_start[256];
-  __shared__ uint64_t wsum[STREAM_NT / 64 + 1];
+  __shared__ PlanLds lds;
   if (p.ctl->status) return;
   const uint64_t n_items = *a.n_items_p;
   for (uint64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
     const Item it = a.items[ii];
-    plan_children(p, a.hist + ii * 256, it.off, 1u - it.src, a.level + 1, a.cursor + ii * 256,
-                  s_start, wsum);
+    plan_children(p, a.hist[ii * 256 + threadIdx.x], it.off, 1u - it.src, a.level + 1,
+                  a.cursor + ii * 256, lds);
   }
 }
 
@@ -579,22 +769,28 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0,
     // keys are placed through LDS, so any assignment of keys to threads works:
     // use the coalesced strided one (valid keys form a prefix of each thread's)
     const int n = load_tile<K>(it.src ? b1 : b0, start, end, keys);
-    partition_tile<K>(keys, n, a.bits, a.level, a.cursor + ii * 256, it.src ? b0 : b1, s);
+    partition_tile<K>(keys, n, a.bits, a.level, a.cursor + ii * 256, 0, it.src ? b0 : b1, s);
   }
 }
 
 // ---------------------------------------------------------------------------
-// 4. LDS-resident sort of each batch: least-significant-digit radix passes over
-// the bits in which the batch's keys differ.  Wave w owns the contiguous chunk
-// [w * 64 * KPT, (w+1) * 64 * KPT) of the batch; within it, element
-// (w * KPT + j) * 64 + lane is held in register j of that lane, so "register j
-// before register j+1, lane order within a register" is the current order.
-// Ranking is stable: a key's rank counts the equal digits before it in that
-// order (earlier registers through a running per-wave count, the same register
-// through the ballot peers in lower lanes), and the waves are laid out in order
-// by an exclusive scan over (digit, wave).  Slots past the batch hold the
-// all-ones key, which is never canonical and, having the largest digit in every
-// pass, stays behind every real key.
+// 4. LDS-resident sort of each batch by most-significant-digit refinement.
+// Keys within a batch agree on every bit above the highest bit in which any two
+// differ (hb), so the batch is first partitioned by the 8 bits below hb by the
+// whole workgroup (LDS histogram, scan, atomic cursors; no stability is needed
+// since equal keys are indistinguishable).  Each resulting segment holds keys
+// that agree above its `shift` and is finished by the cheapest method for its
+// size:
+//   1 key, or no bits left (all keys equal)  -> already sorted;
+//   <= SMALL keys                             -> one lane's sorting network;
+//   <= 64 keys                                -> one wave, each lane ranking its
+//                                                key against the others;
+//   more                                      -> one wave partitions it by its
+//                                                next 8 bits, and its pieces are
+//                                                classified again.
+// Segments are refined in ping-pong between two LDS buffers; every finished
+// segment ends in buffer `a` at its final position, which is written out with
+// coalesced stores.
 
 __device__ __forceinline__ int bit_length(uint64_t x) { return x ? 64 - __clzll(x) : 0; }
 __device__ __forceinline__ int bit_length(u128 x) {
@@ -606,168 +802,411 @@ __device__ __forceinline__ u128 wave_or_key(u128 v) {
   const uint64_t lo = wave_or((uint64_t)v), hi = wave_or((uint64_t)(v >> 64));
   return ((u128)hi << 64) | lo;
 }
+__device__ __forceinline__ uint64_t read_lane_key(uint64_t v, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ u128 read_lane_key(u128 v, int l) {
+  return ((u128)read_lane_key((uint64_t)(v >> 64), l) << 64) | read_lane_key((uint64_t)v, l);
+}
 
+// The 8-bit digit below `shift` (bits [shift-8, shift), fewer when shift < 8).
+template <typename K> __device__ __forceinline__ uint32_t seg_digit(K key, int shift) {
+  if (shift >= 8) return (uint32_t)(key >> (shift - 8)) & 0xffu;
+  return (uint32_t)key & ((1u << shift) - 1u);
+}
+
+// Batcher's odd-even merge sorting network on N registers (N a power of two).
+template <int N, typename K> __device__ __forceinline__ void sort_network(K (&v)[N]) {
+#pragma unroll
+  for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+    for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+      for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k; ++i)
+          if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+            const K x = v[i + j], y = v[i + j + k];
+            const bool sw = y < x;
+            v[i + j] = sw ? y : x;
+            v[i + j + k] = sw ? x : y;
+          }
+}
+
+// Sorting network on (key, count) pairs, ordered by key.
+template <int N, typename K>
+__device__ __forceinline__ void sort_network_kv(K (&v)[N], uint32_t (&c)[N]) {
+#pragma unroll
+  for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+    for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+      for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k; ++i)
+          if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+            const K x = v[i + j], y = v[i + j + k];
+            const uint32_t cx = c[i + j], cy = c[i + j + k];
+            const bool sw = y < x;
+            v[i + j] = sw ? y : x;
+            v[i + j + k] = sw ? x : y;
+            c[i + j] = sw ? cy : cx;
+            c[i + j + k] = sw ? cx : cy;
+          }
+}
+
+// segment descriptor: start, size (16 bits each), shift + 128 (8 bits), buffer (1 bit)
+__device__ __forceinline__ uint64_t seg_pack(uint32_t start, uint32_t size, int shift,
+                                             uint32_t buf) {
+  return (uint64_t)start | ((uint64_t)size << 16) | ((uint64_t)(uint32_t)(shift + 128) << 32) |
+         ((uint64_t)buf << 40);
+}
+__device__ __forceinline__ uint32_t seg_start(uint64_t d) { return (uint32_t)d & 0xffffu; }
+__device__ __forceinline__ uint32_t seg_size(uint64_t d) { return (uint32_t)(d >> 16) & 0xffffu; }
+__device__ __forceinline__ int seg_shift(uint64_t d) { return (int)((d >> 32) & 0xffu) - 128; }
+__device__ __forceinline__ uint32_t seg_buf(uint64_t d) { return (uint32_t)(d >> 40) & 1u; }
+
+__device__ __forceinline__ uint64_t key_hash(uint64_t k) { return k * 0x9E3779B97F4A7C15ull; }
+__device__ __forceinline__ uint64_t key_hash(u128 k) {
+  return ((uint64_t)k ^ ((uint64_t)(k >> 64) * 0xC2B2AE3D27D4EB4Full)) * 0x9E3779B97F4A7C15ull;
+}
+
+// LDS of the bucket sort.  Buffer 0 (key0/cnt0) is where every finished piece
+// of the sorted distinct keys lands; the table region is reused for buffer 1
+// and, at the end, for the expanded keys.
 template <typename K>
 struct LocalLds {
-  K keys[LOCAL_NT * LocalCfg<K>::KPT];
-  uint32_t wcnt[LOCAL_NW][256];
-  K wor[LOCAL_NW];
-  uint32_t wsum[LOCAL_NW + 1];
+  static constexpr int NT = LocalCfg<K>::NT, NW = NT / 64, CAP = LocalCfg<K>::CAP;
+  static constexpr int SLOTS = LocalCfg<K>::SLOTS;
+  static constexpr size_t TBYTES_A = (size_t)SLOTS * 8;
+  static constexpr size_t TBYTES_B = (size_t)CAP * (sizeof(K) + 4);
+  static constexpr size_t TBYTES = TBYTES_A > TBYTES_B ? TBYTES_A : TBYTES_B;
+  K key0[CAP];        // staged keys, then distinct keys (sorted in place)
+  uint32_t cnt0[CAP];
+  alignas(16) unsigned char t[TBYTES];  // hash table | buffer 1 | expanded keys
+  uint32_t hist[NW][256];
+  uint64_t large[2][CAP / 64 + 1];
+  uint64_t mid[CAP / (LocalCfg<K>::SMALL + 1) + 1];
+  uint32_t nlarge[2], nmid, nuniq;
+  K wor[NW];
+  uint32_t wsum[NW + 1];
+  __device__ uint32_t *own() { return reinterpret_cast<uint32_t *>(t); }
+  __device__ uint32_t *tcnt() { return reinterpret_cast<uint32_t *>(t) + SLOTS; }
+  __device__ K *key1() { return reinterpret_cast<K *>(t); }
+  __device__ uint32_t *cnt1() { return reinterpret_cast<uint32_t *>(t + (size_t)CAP * sizeof(K)); }
+  __device__ K *keys_of(uint32_t b) { return b ? key1() : key0; }
+  __device__ uint32_t *cnts_of(uint32_t b) { return b ? cnt1() : cnt0; }
 };
 
+// Finish or enqueue one segment [start, start+c) of distinct keys in buffer `buf`
+// whose keys agree above `shift`.  Called by one lane.
 template <typename K>
-__global__ __launch_bounds__(LOCAL_NT) void k_local_sort(const Batch *batches,
-                                                         const uint64_t *n_batches_p, K *b0,
-                                                         K *b1, const Ctl *ctl) {
-  constexpr int KPT = LocalCfg<K>::KPT;
+__device__ __forceinline__ void classify_segment(LocalLds<K> &s, uint32_t start, uint32_t c,
+                                                 int shift, uint32_t buf, int nxt) {
+  constexpr int SMALL = LocalCfg<K>::SMALL;
+  if (c == 0) return;
+  K *kb = s.keys_of(buf);
+  uint32_t *cb = s.cnts_of(buf);
+  if (c == 1) {
+    if (buf) {
+      s.key0[start] = kb[start];
+      s.cnt0[start] = cb[start];
+    }
+    return;
+  }
+  // distinct keys: c >= 2 always leaves bits to split on (shift > 0)
+  if (c <= (uint32_t)SMALL) {
+    K v[SMALL];
+    uint32_t w[SMALL];
+#pragma unroll
+    for (int j = 0; j < SMALL; ++j) {
+      const bool in = (uint32_t)j < c;
+      v[j] = in ? kb[start + j] : all_ones<K>();
+      w[j] = in ? cb[start + j] : 0u;
+    }
+    sort_network_kv<SMALL, K>(v, w);
+#pragma unroll
+    for (int j = 0; j < SMALL; ++j)
+      if ((uint32_t)j < c) {
+        s.key0[start + j] = v[j];
+        s.cnt0[start + j] = w[j];
+      }
+  } else if (c <= 64) {
+    s.mid[atomicAdd(&s.nmid, 1u)] = seg_pack(start, c, shift, buf);
+  } else {
+    s.large[nxt][atomicAdd(&s.nlarge[nxt], 1u)] = seg_pack(start, c, shift, buf);
+  }
+}
+
+// Sort a batch of up to CAP keys (consecutive small buckets) in LDS:
+//  1. stage the keys; insert each into an LDS hash table keyed by the index of
+//     the first occurrence (whose staged key is compared), counting duplicates;
+//  2. compact the distinct keys with their counts;
+//  3. partition the distinct keys by the 8 bits below the highest bit in which
+//     they differ (whole workgroup), then finish each piece: up to SMALL keys by
+//     one lane's sorting network, up to 64 by one wave ranking each key against
+//     the others, larger ones by a wave partition on their next 8 bits;
+//  4. write the sorted distinct keys and their counts over the batch's first
+//     positions and mark those positions in the bitmap.
+// Bits [off, off + nu) of the bitmap set, the rest of [off, off + m) left
+// clear (the bitmap starts zeroed).  Words wholly inside the range belong to
+// this batch alone and are stored; the two boundary words are or-ed.
+__device__ __forceinline__ void mark_positions(uint32_t *bits, uint64_t off, uint32_t m,
+                                               uint32_t nu) {
+  const uint64_t w0 = off >> 5, w1 = (off + m - 1) >> 5;
+  for (uint64_t wi = w0 + threadIdx.x; wi <= w1; wi += blockDim.x) {
+    const uint64_t p0 = wi << 5;
+    const uint64_t lo = off > p0 ? off : p0;              // first position of the batch in the word
+    const uint64_t hi_set = off + nu < p0 + 32 ? off + nu : p0 + 32;
+    uint32_t mask = 0;
+    if (hi_set > lo) {
+      const uint32_t a = (uint32_t)(lo - p0), c = (uint32_t)(hi_set - lo);
+      mask = (c == 32 ? 0xffffffffu : ((1u << c) - 1u)) << a;
+    }
+    const bool inside = off <= p0 && p0 + 32 <= off + m;
+    if (inside) bits[wi] = mask;
+    else if (mask) atomicOr(&bits[wi], mask);
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *batches,
+                                                                const uint64_t *n_batches_p,
+                                                                K *b0, K *b1, uint32_t *bits,
+                                                                const Ctl *ctl) {
+  using Cfg = LocalCfg<K>;
+  constexpr int NT = Cfg::NT, NW = NT / 64, SLOTS = Cfg::SLOTS;
+  constexpr uint32_t EMPTY = 0xffffffffu;
+  constexpr int SPT = (SLOTS + NT - 1) / NT;
   __shared__ LocalLds<K> s;
   if (ctl->status) return;
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-  const uint64_t lt = lanemask_lt();
   const uint64_t n_batches = *n_batches_p;
+  uint32_t *own = s.own(), *tcnt = s.tcnt();
   for (uint64_t bi = blockIdx.x; bi < n_batches; bi += gridDim.x) {
-    const Batch b = batches[bi];
-    const K *src = b.src ? b1 : b0;
-    const uint32_t m = b.size;
-    const uint32_t nwa = (m + 64u * KPT - 1) / (64u * KPT);  // waves holding elements
-    const bool active = w < nwa;
-    K kv[KPT];
-    K diff = 0;
-    const K k0 = src[b.off];
-#pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-      const uint32_t e = (w * KPT + j) * 64 + lane;
-      kv[j] = e < m ? src[b.off + e] : all_ones<K>();
-      if (e < m) diff |= kv[j] ^ k0;
+    const Batch bt = batches[bi];
+    const K *src = bt.src ? b1 : b0;
+    const uint32_t m = bt.size;
+    // 1. stage and hash
+    for (uint32_t e = tid; e < m; e += NT) s.key0[e] = src[bt.off + e];
+    for (uint32_t q = tid; q < (uint32_t)SLOTS; q += NT) {
+      own[q] = EMPTY;
+      tcnt[q] = 0;
     }
+    if (tid == 0) {
+      s.nlarge[0] = s.nlarge[1] = 0;
+      s.nmid = 0;
+    }
+    __syncthreads();
+    {
+      // first probe of every key of this thread at once (independent LDS
+      // atomics in flight), then linear probing for the few that collided
+      constexpr int KPT = (LocalCfg<K>::CAP + NT - 1) / NT;
+      uint32_t hs[KPT], os[KPT];
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const uint32_t e = tid + (uint32_t)j * NT;
+        hs[j] = 0;
+        os[j] = EMPTY;
+        if (e < m) {
+          hs[j] = (uint32_t)(((key_hash(s.key0[e]) >> 32) * (uint64_t)SLOTS) >> 32);
+          os[j] = atomicCAS(&own[hs[j]], EMPTY, e);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const uint32_t e = tid + (uint32_t)j * NT;
+        if (e < m) {
+          const K key = s.key0[e];
+          uint32_t h = hs[j], o = os[j];
+          while (o != EMPTY && s.key0[o] != key) {
+            h = h + 1 == (uint32_t)SLOTS ? 0u : h + 1;
+            o = atomicCAS(&own[h], EMPTY, e);
+          }
+          atomicAdd(&tcnt[h], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    // 2. compact: thread t owns slots [t*SPT, (t+1)*SPT)
+    K uk[SPT];
+    uint32_t uc[SPT];
+    uint32_t nv = 0;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const uint32_t q = tid * SPT + j;
+      const uint32_t o = q < (uint32_t)SLOTS ? own[q] : EMPTY;
+      uc[j] = o != EMPTY ? tcnt[q] : 0u;
+      uk[j] = o != EMPTY ? s.key0[o] : K(0);
+      nv += o != EMPTY ? 1u : 0u;
+    }
+    uint32_t nu;
+    uint32_t pos = block_exclusive_scan<NT>(nv, s.wsum, &nu);
+    // (the scan's barriers separate the reads above from the writes below)
+    K diff = 0;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j)
+      if (uc[j]) {
+        s.key0[pos] = uk[j];
+        s.cnt0[pos] = uc[j];
+        ++pos;
+      }
+    __syncthreads();
+    // highest differing bit among the distinct keys
+    const K k0 = s.key0[0];
+    for (uint32_t u = tid; u < nu; u += NT) diff |= s.key0[u] ^ k0;
     diff = wave_or_key(diff);
     if (lane == 0) s.wor[w] = diff;
+    if (tid < 256) s.hist[0][tid] = 0;
     __syncthreads();
     K all = 0;
 #pragma unroll
-    for (int i = 0; i < LOCAL_NW; ++i) all |= s.wor[i];
-    const int passes = (bit_length(all) + 7) >> 3;
-    for (int p = 0; p < passes; ++p) {
-      const int shift = 8 * p;
-      uint32_t dg[KPT], rank[KPT];
-      if (active) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s.wcnt[w][lane + 64 * q] = 0;
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-          const uint32_t d = (uint32_t)(kv[j] >> shift) & 0xffu;
-          const uint64_t peers = match_digit8(d);
-          const uint32_t before = (uint32_t)__popcll(peers & lt);
-          const uint32_t base = s.wcnt[w][d];
-          if (before == 0) s.wcnt[w][d] = base + (uint32_t)__popcll(peers);
-          dg[j] = d;
-          rank[j] = base + before;
-        }
-      }
+    for (int i = 0; i < NW; ++i) all |= s.wor[i];
+    const int hb = bit_length(all);
+    int cur = 0;
+    if (hb > 0) {
+      // 3. whole-workgroup partition of the distinct keys into buffer 1
+      K *k1 = s.key1();
+      uint32_t *c1 = s.cnt1();
+      for (uint32_t u = tid; u < nu; u += NT) atomicAdd(&s.hist[0][seg_digit(s.key0[u], hb)], 1u);
       __syncthreads();
-      uint32_t run = 0;
-      if (tid < 256)
-        for (uint32_t v = 0; v < nwa; ++v) {
-          const uint32_t c = s.wcnt[v][tid];
-          s.wcnt[v][tid] = run;
-          run += c;
-        }
+      const uint32_t c = tid < 256 ? s.hist[0][tid] : 0u;
       uint32_t tot;
-      const uint32_t dbase = block_exclusive_scan<LOCAL_NT>(tid < 256 ? run : 0u, s.wsum, &tot);
-      if (tid < 256)
-        for (uint32_t v = 0; v < nwa; ++v) s.wcnt[v][tid] += dbase;
+      const uint32_t st = block_exclusive_scan<NT>(c, s.wsum, &tot);
+      if (tid < 256) s.hist[0][tid] = st;
       __syncthreads();
-      if (active) {
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) s.keys[s.wcnt[w][dg[j]] + rank[j]] = kv[j];
+      for (uint32_t u = tid; u < nu; u += NT) {
+        const K key = s.key0[u];
+        const uint32_t q = atomicAdd(&s.hist[0][seg_digit(key, hb)], 1u);
+        k1[q] = key;
+        c1[q] = s.cnt0[u];
       }
       __syncthreads();
-      if (active) {
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) kv[j] = s.keys[(w * KPT + j) * 64 + lane];
-      }
+      if (tid < 256) classify_segment<K>(s, st, c, hb - 8, 1u, 0);
     }
-    if (active) {
-#pragma unroll
-      for (int j = 0; j < KPT; ++j) {
-        const uint32_t e = (w * KPT + j) * 64 + lane;
-        if (e < m) b0[b.off + e] = kv[j];
+    while (true) {
+      __syncthreads();
+      // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
+      for (uint32_t i = w; i < s.nmid; i += NW) {
+        const uint64_t d = s.mid[i];
+        const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
+        const K *kb = s.keys_of(buf);
+        const uint32_t *cb = s.cnts_of(buf);
+        {
+          const uint32_t me = lane;
+          const K x = me < c ? kb[st + me] : all_ones<K>();
+          const uint32_t xc = me < c ? cb[st + me] : 0u;
+          uint32_t rank = 0;
+          for (uint32_t j = 0; j < c; ++j) rank += kb[st + j] < x ? 1u : 0u;
+          // c <= 64, so this loop runs once: when the piece is already in
+          // buffer 0 the wave's reads above precede its writes below (LDS
+          // operations of one wave complete in order)
+          if (me < c) {
+            s.key0[st + rank] = x;
+            s.cnt0[st + rank] = xc;
+          }
+        }
       }
+      __syncthreads();
+      if (tid == 0) s.nmid = 0;
+      const uint32_t nl = s.nlarge[cur];
+      __syncthreads();
+      if (nl == 0) break;
+      // larger pieces: one wave each, partitioned by the 8 bits below their
+      // highest differing bit into the other buffer
+      for (uint32_t i = w; i < nl; i += NW) {
+        const uint64_t d = s.large[cur][i];
+        const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
+        const K *ik = s.keys_of(buf);
+        const uint32_t *ic = s.cnts_of(buf);
+        K *ok = s.keys_of(buf ^ 1u);
+        uint32_t *oc = s.cnts_of(buf ^ 1u);
+        uint32_t *h = s.hist[w];
+        K dd = 0;
+        const K kk = ik[st];
+        for (uint32_t e = lane; e < c; e += 64) dd |= ik[st + e] ^ kk;
+        const int shift = bit_length(wave_or_key(dd));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[lane + 64 * q] = 0;
+        for (uint32_t e = lane; e < c; e += 64) atomicAdd(&h[seg_digit(ik[st + e], shift)], 1u);
+        uint32_t cnt[4], pre[4], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cnt[q] = h[4 * lane + q];
+          pre[q] = sum;
+          sum += cnt[q];
+        }
+        const uint32_t base = st + wave_inclusive_scan(sum) - sum;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[4 * lane + q] = base + pre[q];
+        for (uint32_t e = lane; e < c; e += 64) {
+          const K key = ik[st + e];
+          const uint32_t q = atomicAdd(&h[seg_digit(key, shift)], 1u);
+          ok[q] = key;
+          oc[q] = ic[st + e];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          classify_segment<K>(s, base + pre[q], cnt[q], shift - 8, buf ^ 1u, cur ^ 1);
+      }
+      __syncthreads();
+      if (tid == 0) s.nlarge[cur] = 0;
+      cur ^= 1;
     }
+    __syncthreads();
+    // 4. the batch's distinct keys, sorted, replace its first positions in
+    //    buffer 0, their counts go to the same positions of buffer 1, and the
+    //    bitmap marks those positions
+    for (uint32_t u = tid; u < nu; u += NT) {
+      b0[bt.off + u] = s.key0[u];
+      b1[bt.off + u] = (K)s.cnt0[u];
+    }
+    mark_positions(bits, bt.off, m, nu);
     __syncthreads();
   }
 }
 
-// Oversized buckets whose digits are exhausted hold one key repeated: they are
-// already sorted and only need to be in buffer 0.
+// Oversized buckets whose digits are exhausted hold one key repeated: one
+// distinct key whose count is the bucket size.
 template <typename K>
-__global__ void k_uniform_copy(const Item *uni, const uint64_t *n_uni_p, K *b0, const K *b1,
-                               const Ctl *ctl) {
+__global__ void k_uniform_emit(const Item *uni, const uint64_t *n_uni_p, K *b0, K *b1,
+                               uint32_t *bits, const Ctl *ctl) {
   if (ctl->status) return;
   const uint64_t n = *n_uni_p;
-  for (uint64_t u = 0; u < n; ++u) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < n;
+       u += (uint64_t)gridDim.x * blockDim.x) {
     const Item it = uni[u];
-    if (it.src == 0) continue;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < it.size;
-         i += (uint64_t)gridDim.x * blockDim.x)
-      b0[it.off + i] = b1[it.off + i];
+    const K key = (it.src ? b1 : b0)[it.off];
+    b0[it.off] = key;
+    b1[it.off] = (K)it.size;
+    atomicOr(&bits[it.off >> 5], 1u << (it.off & 31));
   }
 }
 
 // ---------------------------------------------------------------------------
-// 5. Run-length reduce of the sorted keys.  Position i starts a run when it is
-// the first key of a read set or differs from key i-1.  Thread q of tile t owns
-// positions [t*TILE + q*KPT, +KPT).
+// 5. Emit the tables.  Every position marked in the bitmap holds a distinct key
+// (buffer 0) and its count (buffer 1), and marked positions are in key order
+// within each read set, so the output row of a marked position is the number of
+// marked positions before it.  Tiles of TILE positions (128 bitmap words, one
+// per thread).
 
-struct RleArgs {
-  const uint64_t *set_kbase;
-  uint64_t n_sets;
-  uint64_t *tile_heads;
-  uint64_t *hpos;  // position of the first key of each run, plus hpos[U] = n
-};
+constexpr int EMIT_NT = (int)(TILE / 32);
 
-template <typename K>
-__device__ __forceinline__ uint32_t run_heads(const K *keys, uint64_t n, const RleArgs &a,
-                                              uint64_t i0, K (&kv)[STREAM_KPT]) {
-  uint32_t flags = 0;
-  if (i0 >= n) return 0;
-  uint64_t ns = lower_bound(a.set_kbase, 0, a.n_sets + 1, i0);
-  uint64_t bnd = ns <= a.n_sets ? a.set_kbase[ns] : ~0ull;
-  K prev = i0 ? keys[i0 - 1] : K(0);
-#pragma unroll
-  for (int r = 0; r < STREAM_KPT; ++r) {
-    const uint64_t i = i0 + r;
-    if (i < n) {
-      kv[r] = keys[i];
-      bool h = (i == 0) || kv[r] != prev;
-      if (i == bnd) {
-        h = true;
-        while (ns <= a.n_sets && a.set_kbase[ns] == i) ++ns;
-        bnd = ns <= a.n_sets ? a.set_kbase[ns] : ~0ull;
-      }
-      if (h) flags |= 1u << r;
-      prev = kv[r];
-    }
-  }
-  return flags;
-}
-
-template <typename K>
-__global__ __launch_bounds__(STREAM_NT) void k_rle_count(const K *keys, RleArgs a,
-                                                         const Ctl *ctl) {
-  __shared__ uint64_t wsum[STREAM_NT / 64 + 1];
+__global__ __launch_bounds__(EMIT_NT) void k_emit_count(const uint32_t *bits, uint64_t *tile_cnt,
+                                                        const Ctl *ctl) {
+  __shared__ uint64_t wsum[EMIT_NT / 64 + 1];
   if (ctl->status) return;
-  const uint64_t n = ctl->n_keys;
-  const uint64_t i0 = blockIdx.x * TILE + threadIdx.x * (uint64_t)STREAM_KPT;
-  K kv[STREAM_KPT];
-  const uint32_t f = run_heads<K>(keys, n, a, i0, kv);
+  const uint32_t c = (uint32_t)__popc(bits[blockIdx.x * (uint64_t)EMIT_NT + threadIdx.x]);
   uint64_t tot;
-  block_exclusive_scan<STREAM_NT>((uint64_t)__popc(f), wsum, &tot);
-  if (threadIdx.x == 0) a.tile_heads[blockIdx.x] = tot;
+  block_exclusive_scan<EMIT_NT>((uint64_t)c, wsum, &tot);
+  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
 }
 
 struct OutArgs {
   void *kmer;        // nodes: key per row
+  uint32_t *count;   // nodes: count; edges: multiplicity
   void *u, *v;       // edges
   uint8_t *orient;
   void *zkey;        // optional
@@ -776,57 +1215,65 @@ struct OutArgs {
 };
 
 template <typename K, bool EDGES>
-__global__ __launch_bounds__(STREAM_NT) void k_rle_write(const K *keys, RleArgs a, OutArgs o,
-                                                         const Ctl *ctl) {
-  __shared__ uint64_t wsum[STREAM_NT / 64 + 1];
+__global__ __launch_bounds__(EMIT_NT) void k_emit_write(const uint32_t *bits,
+                                                        const uint64_t *tile_base, const K *b0,
+                                                        const K *b1, OutArgs o, const Ctl *ctl) {
+  // gather the tile's distinct keys and counts in order into LDS, then write
+  // the output rows with consecutive threads on consecutive rows
+  __shared__ K sk[TILE];
+  __shared__ uint32_t sc[TILE];
+  __shared__ uint64_t wsum[EMIT_NT / 64 + 1];
   if (ctl->status) return;
-  const uint64_t n = ctl->n_keys;
-  const uint64_t i0 = blockIdx.x * TILE + threadIdx.x * (uint64_t)STREAM_KPT;
-  K kv[STREAM_KPT];
-  const uint32_t f = run_heads<K>(keys, n, a, i0, kv);
+  const uint64_t wi = blockIdx.x * (uint64_t)EMIT_NT + threadIdx.x;
+  uint32_t word = bits[wi];
   uint64_t tot;
-  uint64_t j = block_exclusive_scan<STREAM_NT>((uint64_t)__popc(f), wsum, &tot) +
-               a.tile_heads[blockIdx.x];
-#pragma unroll
-  for (int r = 0; r < STREAM_KPT; ++r) {
-    if (f & (1u << r)) {
-      a.hpos[j] = i0 + r;
-      if (j < o.capacity) {
-        if (EDGES) {
-          K u, v;
-          uint32_t orient;
-          decode_edge(kv[r], o.k, &u, &v, &orient);
-          static_cast<K *>(o.u)[j] = u;
-          static_cast<K *>(o.v)[j] = v;
-          o.orient[j] = (uint8_t)orient;
-          if (o.zkey) static_cast<K *>(o.zkey)[j] = kv[r];
-        } else {
-          static_cast<K *>(o.kmer)[j] = kv[r];
-        }
-      }
-      ++j;
+  uint32_t r = (uint32_t)block_exclusive_scan<EMIT_NT>((uint64_t)__popc(word), wsum, &tot);
+  while (word) {
+    const int b = __ffs(word) - 1;
+    word &= word - 1;
+    const uint64_t pos = (wi << 5) + (uint64_t)b;
+    sk[r] = b0[pos];
+    sc[r] = (uint32_t)b1[pos];
+    ++r;
+  }
+  __syncthreads();
+  const uint64_t base = tile_base[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)tot; i += EMIT_NT) {
+    const uint64_t j = base + i;
+    if (j >= o.capacity) break;
+    const K key = sk[i];
+    o.count[j] = sc[i];
+    if (EDGES) {
+      K u, v;
+      uint32_t orient;
+      decode_edge(key, o.k, &u, &v, &orient);
+      static_cast<K *>(o.u)[j] = u;
+      static_cast<K *>(o.v)[j] = v;
+      o.orient[j] = (uint8_t)orient;
+      if (o.zkey) static_cast<K *>(o.zkey)[j] = key;
+    } else {
+      static_cast<K *>(o.kmer)[j] = key;
     }
   }
-  if (n && i0 <= n - 1 && n - 1 < i0 + STREAM_KPT) a.hpos[ctl->n_unique] = n;
 }
 
-// counts / multiplicities from run starts; per-set row offsets; result counters.
-__global__ void k_finalize(const uint64_t *hpos, uint32_t *count, uint64_t capacity,
+// Row offset of each read set: marked positions before its first key.
+__global__ void k_set_rows(const uint32_t *bits, const uint64_t *tile_base,
+                           const uint64_t *set_kbase, uint64_t n_sets, uint64_t *set_rows,
                            const Ctl *ctl) {
-  if (ctl->status) return;
-  const uint64_t u = ctl->n_unique;
-  const uint64_t lim = u < capacity ? u : capacity;
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < lim;
-       j += (uint64_t)gridDim.x * blockDim.x)
-    count[j] = (uint32_t)(hpos[j + 1] - hpos[j]);
-}
-
-__global__ void k_set_uoff(const uint64_t *hpos, const uint64_t *set_kbase, uint64_t n_sets,
-                           uint64_t *set_uoff, const Ctl *ctl) {
-  if (ctl->status || !set_uoff) return;
+  if (ctl->status || !set_rows) return;
   const uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (s > n_sets) return;
-  set_uoff[s] = lower_bound(hpos, 0, ctl->n_unique, set_kbase[s]);
+  const uint64_t p = set_kbase[s];
+  if (p >= ctl->n_keys) {
+    set_rows[s] = ctl->n_unique;
+    return;
+  }
+  const uint64_t t = p / TILE;
+  uint64_t r = tile_base[t];
+  for (uint64_t wi = t * EMIT_NT; wi < (p >> 5); ++wi) r += (uint64_t)__popc(bits[wi]);
+  if (p & 31) r += (uint64_t)__popc(bits[p >> 5] & ((1u << (p & 31)) - 1u));
+  set_rows[s] = r;
 }
 
 __global__ void k_table_done(Ctl *ctl, int edges, uint64_t capacity) {
@@ -914,7 +1361,8 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   uint64_t *set_tbase = reinterpret_cast<uint64_t *>(ws + L.set_tbase);
   uint64_t *tile_read = reinterpret_cast<uint64_t *>(ws + L.tile_read);
   uint32_t *tile_set = reinterpret_cast<uint32_t *>(ws + L.tile_set);
-  uint64_t *hist0 = reinterpret_cast<uint64_t *>(ws + L.hist0);
+  uint32_t *thist = reinterpret_cast<uint32_t *>(ws + L.thist);
+  uint32_t *csum = reinterpret_cast<uint32_t *>(ws + L.csum);
   uint64_t *cursor0 = reinterpret_cast<uint64_t *>(ws + L.cursor0);
   Item *items[2] = {reinterpret_cast<Item *>(ws + L.items[0]),
                     reinterpret_cast<Item *>(ws + L.items[1])};
@@ -926,7 +1374,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   uint64_t *rle_heads = reinterpret_cast<uint64_t *>(ws + L.rle_heads);
   K *x0 = reinterpret_cast<K *>(ws + L.keys[0]);
   K *x1 = reinterpret_cast<K *>(ws + L.keys[1]);
-  uint64_t *hpos = reinterpret_cast<uint64_t *>(ws + L.keys[1]);
+  uint32_t *runbits = reinterpret_cast<uint32_t *>(ws + L.bits);
   hipStream_t st = A.stream;
   const uint64_t S = A.n_sets;
   const int len = edges ? A.k + 1 : A.k;
@@ -943,8 +1391,6 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                      A.read_offsets, A.n_reads, len, block_sums, rbase, ctl);
   hipLaunchKernelGGL(k_set_setup, dim3(1), dim3(1024), 0, st, rbase, A.n_reads, set_read_off, S,
                      A.max_keys, set_kbase, set_tbase, ctl);
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(S * 256, 256, 4096)), dim3(256), 0, st, hist0,
-                     S * 256, 0ull);
   hipLaunchKernelGGL(k_tile_map, dim3(grid_for(L.max_tiles, 256, 1u << 30)), dim3(256), 0, st,
                      rbase, set_read_off, S, set_kbase, set_tbase, tile_read, tile_set,
                      L.max_tiles, ctl);
@@ -952,17 +1398,21 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   EnumArgs ea{A.packed, (A.n_bases + 31) / 32, A.read_offsets, rbase, set_read_off, set_kbase,
               set_tbase, tile_read, tile_set, len, bits};
   hipLaunchKernelGGL(k_enum_hist<K>, dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st, ea,
-                     hist0, ctl);
+                     thist, ctl);
   stage(ev + 2, st);
+  const unsigned col_chunks = (unsigned)((L.max_tiles + COL_CHUNK - 1) / COL_CHUNK);
+  hipLaunchKernelGGL(k_col_reduce, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl);
+  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, ctl);
+  hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl);
   PlanArgs pa{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
               uniform, L.item_cap, ctl, local_cap<K>(), bits};
-  hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, hist0,
-                     cursor0, set_kbase, S);
+  hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
+                     set_tbase, cursor0, set_kbase, S);
   stage(ev + 3, st);
   hipLaunchKernelGGL(k_enum_scatter<K>, dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st, ea,
-                     cursor0, x0, ctl);
+                     cursor0, thist, x0, ctl);
   stage(ev + 4, st);
-  const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 8192);
+  const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 2048);
   for (int lev = 1; bits - 8 * lev > 0; ++lev) {
     const int li = lev & 1;
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[li], &ctl->items[li],
@@ -971,51 +1421,49 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
     PlanArgs pl{items[li ^ 1], &ctl->items[li ^ 1], hist[li ^ 1], L.item_cap, batches,
                 L.batch_cap, uniform, L.item_cap, ctl, local_cap<K>(), bits};
-    hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 4096)), dim3(STREAM_NT), 0, st,
+    hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
                        pl, la);
     hipLaunchKernelGGL(k_level_scatter<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1,
                        ctl);
   }
   stage(ev + 5, st);
-  hipLaunchKernelGGL(k_local_sort<K>, dim3(grid_for(L.batch_cap, 1, 2048)), dim3(LOCAL_NT), 0, st,
-                     batches, &ctl->n_batches, x0, x1, ctl);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.rle_tiles * (TILE / 64), 256, 8192)), dim3(256), 0,
+                     st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
+  hipLaunchKernelGGL(k_local_sort<K>, dim3(grid_for(L.batch_cap, 1, 2048)), dim3(LocalCfg<K>::NT),
+                     0, st, batches, &ctl->n_batches, x0, x1, runbits, ctl);
   stage(ev + 6, st);
-  hipLaunchKernelGGL(k_uniform_copy<K>, dim3(1024), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
-                     x1, ctl);
-  RleArgs ra{set_kbase, S, rle_heads, hpos};
-  hipLaunchKernelGGL(k_rle_count<K>, dim3((unsigned)L.rle_tiles), dim3(STREAM_NT), 0, st, x0, ra,
-                     ctl);
+  hipLaunchKernelGGL(k_uniform_emit<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
+                     x1, runbits, ctl);
+  hipLaunchKernelGGL(k_emit_count, dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st, runbits,
+                     rle_heads, ctl);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, rle_heads, L.rle_tiles,
                      &ctl->n_unique);
   stage(ev + 7, st);
   OutArgs oa{};
   oa.k = A.k;
-  uint32_t *count;
   uint64_t capacity;
-  uint64_t *set_uoff;
+  uint64_t *set_rows;
   if (edges) {
     oa.u = A.edges.u;
     oa.v = A.edges.v;
     oa.orient = A.edges.orient;
     oa.zkey = A.edges.zkey;
+    oa.count = A.edges.mult;
     oa.capacity = capacity = A.edges.capacity;
-    count = A.edges.mult;
-    set_uoff = A.edge_set_offsets;
-    hipLaunchKernelGGL((k_rle_write<K, true>), dim3((unsigned)L.rle_tiles), dim3(STREAM_NT), 0,
-                       st, x0, ra, oa, ctl);
+    set_rows = A.edge_set_offsets;
+    hipLaunchKernelGGL((k_emit_write<K, true>), dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st,
+                       runbits, rle_heads, x0, x1, oa, ctl);
   } else {
     oa.kmer = A.nodes.kmer;
+    oa.count = A.nodes.count;
     oa.capacity = capacity = A.nodes.capacity;
-    count = A.nodes.count;
-    set_uoff = A.node_set_offsets;
-    hipLaunchKernelGGL((k_rle_write<K, false>), dim3((unsigned)L.rle_tiles), dim3(STREAM_NT), 0,
-                       st, x0, ra, oa, ctl);
+    set_rows = A.node_set_offsets;
+    hipLaunchKernelGGL((k_emit_write<K, false>), dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st,
+                       runbits, rle_heads, x0, x1, oa, ctl);
   }
   stage(ev + 8, st);
-  hipLaunchKernelGGL(k_finalize, dim3(grid_for(A.max_keys, 256, 65536)), dim3(256), 0, st, hpos,
-                     count, capacity, ctl);
-  hipLaunchKernelGGL(k_set_uoff, dim3(grid_for(S + 1, 256, 1u << 30)), dim3(256), 0, st, hpos,
-                     set_kbase, S, set_uoff, ctl);
+  hipLaunchKernelGGL(k_set_rows, dim3(grid_for(S + 1, 256, 1u << 30)), dim3(256), 0, st, runbits,
+                     rle_heads, set_kbase, S, set_rows, ctl);
   hipLaunchKernelGGL(k_table_done, dim3(1), dim3(1), 0, st, ctl, edges ? 1 : 0, capacity);
   stage(ev + 9, st);
   return hipGetLastError();
