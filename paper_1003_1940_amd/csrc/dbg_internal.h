@@ -30,7 +30,7 @@ template <> struct LocalCfg<unsigned __int128> {
   static constexpr int NT = 512;
   static constexpr int CAP = 3072;
   static constexpr int SLOTS = 4608;
-  static constexpr int SMALL = 16;
+  static constexpr int SMALL = 8;
 };
 template <typename K> constexpr uint64_t local_cap() { return (uint64_t)LocalCfg<K>::CAP; }
 

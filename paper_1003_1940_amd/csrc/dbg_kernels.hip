@@ -980,17 +980,40 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
   constexpr int NT = Cfg::NT, NW = NT / 64, SLOTS = Cfg::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
   constexpr int SPT = (SLOTS + NT - 1) / NT;
+  constexpr int LPT = (LocalCfg<K>::CAP + NT - 1) / NT;  // keys per thread
   __shared__ LocalLds<K> s;
   if (ctl->status) return;
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const uint64_t n_batches = *n_batches_p;
+  const uint64_t G = gridDim.x;
   uint32_t *own = s.own(), *tcnt = s.tcnt();
-  for (uint64_t bi = blockIdx.x; bi < n_batches; bi += gridDim.x) {
-    const Batch bt = batches[bi];
-    const K *src = bt.src ? b1 : b0;
+  // software pipeline: the keys of the next batch are loaded into registers
+  // while this one is processed in LDS (descriptors are read two batches ahead)
+  K pre[LPT];
+  auto prefetch = [&](const Batch &b) {
+    const K *src = b.src ? b1 : b0;
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      const uint32_t e = tid + (uint32_t)j * NT;
+      pre[j] = e < b.size ? src[b.off + e] : K(0);
+    }
+  };
+  const Batch none = {0, 0, 0};
+  Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
+  prefetch(nxt);
+  Batch nxt2 = blockIdx.x + G < n_batches ? batches[blockIdx.x + G] : none;
+  for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
+    const Batch bt = nxt;
     const uint32_t m = bt.size;
     // 1. stage and hash
-    for (uint32_t e = tid; e < m; e += NT) s.key0[e] = src[bt.off + e];
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      const uint32_t e = tid + (uint32_t)j * NT;
+      if (e < m) s.key0[e] = pre[j];
+    }
+    nxt = nxt2;
+    nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
+    if (bi + G < n_batches) prefetch(nxt);
     for (uint32_t q = tid; q < (uint32_t)SLOTS; q += NT) {
       own[q] = EMPTY;
       tcnt[q] = 0;
