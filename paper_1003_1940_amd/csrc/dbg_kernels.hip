@@ -798,6 +798,15 @@ __device__ __forceinline__ int bit_length(u128 x) {
   return hi ? 128 - __clzll(hi) : (lo ? 64 - __clzll(lo) : 0);
 }
 __device__ __forceinline__ uint64_t wave_or_key(uint64_t v) { return wave_or(v); }
+__device__ __forceinline__ uint64_t wave_and_key(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v &= __shfl_xor(v, d, 64);
+  return v;
+}
+__device__ __forceinline__ u128 wave_and_key(u128 v) {
+  const uint64_t lo = wave_and_key((uint64_t)v), hi = wave_and_key((uint64_t)(v >> 64));
+  return ((u128)hi << 64) | lo;
+}
 __device__ __forceinline__ u128 wave_or_key(u128 v) {
   const uint64_t lo = wave_or((uint64_t)v), hi = wave_or((uint64_t)(v >> 64));
   return ((u128)hi << 64) | lo;
@@ -881,23 +890,25 @@ struct LocalLds {
   static constexpr int NT = LocalCfg<K>::NT, NW = NT / 64, CAP = LocalCfg<K>::CAP;
   static constexpr int SLOTS = LocalCfg<K>::SLOTS;
   static constexpr size_t TBYTES_A = (size_t)SLOTS * 8;
-  static constexpr size_t TBYTES_B = (size_t)CAP * (sizeof(K) + 4);
+  static constexpr size_t TBYTES_B = (size_t)CAP * (sizeof(K) + 2);
   static constexpr size_t TBYTES = TBYTES_A > TBYTES_B ? TBYTES_A : TBYTES_B;
   K key0[CAP];        // staged keys, then distinct keys (sorted in place)
-  uint32_t cnt0[CAP];
-  alignas(16) unsigned char t[TBYTES];  // hash table | buffer 1 | expanded keys
+  uint16_t cnt0[CAP];
+  uint16_t ulist[CAP];  // table slot of each distinct key, in discovery order
+  alignas(16) unsigned char t[TBYTES];  // hash table | buffer 1
   uint32_t hist[NW][256];
   uint64_t large[2][CAP / 64 + 1];
   uint64_t mid[CAP / (LocalCfg<K>::SMALL + 1) + 1];
-  uint32_t nlarge[2], nmid, nuniq;
+  uint32_t nlarge[2], nmid, nuniq, dirty;
   K wor[NW];
+  K wand[NW];
   uint32_t wsum[NW + 1];
   __device__ uint32_t *own() { return reinterpret_cast<uint32_t *>(t); }
   __device__ uint32_t *tcnt() { return reinterpret_cast<uint32_t *>(t) + SLOTS; }
   __device__ K *key1() { return reinterpret_cast<K *>(t); }
-  __device__ uint32_t *cnt1() { return reinterpret_cast<uint32_t *>(t + (size_t)CAP * sizeof(K)); }
+  __device__ uint16_t *cnt1() { return reinterpret_cast<uint16_t *>(t + (size_t)CAP * sizeof(K)); }
   __device__ K *keys_of(uint32_t b) { return b ? key1() : key0; }
-  __device__ uint32_t *cnts_of(uint32_t b) { return b ? cnt1() : cnt0; }
+  __device__ uint16_t *cnts_of(uint32_t b) { return b ? cnt1() : cnt0; }
 };
 
 // Finish or enqueue one segment [start, start+c) of distinct keys in buffer `buf`
@@ -908,7 +919,7 @@ __device__ __forceinline__ void classify_segment(LocalLds<K> &s, uint32_t start,
   constexpr int SMALL = LocalCfg<K>::SMALL;
   if (c == 0) return;
   K *kb = s.keys_of(buf);
-  uint32_t *cb = s.cnts_of(buf);
+  uint16_t *cb = s.cnts_of(buf);
   if (c == 1) {
     if (buf) {
       s.key0[start] = kb[start];
@@ -931,7 +942,7 @@ __device__ __forceinline__ void classify_segment(LocalLds<K> &s, uint32_t start,
     for (int j = 0; j < SMALL; ++j)
       if ((uint32_t)j < c) {
         s.key0[start + j] = v[j];
-        s.cnt0[start + j] = w[j];
+        s.cnt0[start + j] = (uint16_t)w[j];
       }
   } else if (c <= 64) {
     s.mid[atomicAdd(&s.nmid, 1u)] = seg_pack(start, c, shift, buf);
@@ -941,13 +952,15 @@ __device__ __forceinline__ void classify_segment(LocalLds<K> &s, uint32_t start,
 }
 
 // Sort a batch of up to CAP keys (consecutive small buckets) in LDS:
-//  1. stage the keys; insert each into an LDS hash table keyed by the index of
-//     the first occurrence (whose staged key is compared), counting duplicates;
-//  2. compact the distinct keys with their counts;
-//  3. partition the distinct keys by the 8 bits below the highest bit in which
-//     they differ (whole workgroup), then finish each piece: up to SMALL keys by
-//     one lane's sorting network, up to 64 by one wave ranking each key against
-//     the others, larger ones by a wave partition on their next 8 bits;
+//  1. stage the keys (prefetched into registers during the previous batch) and
+//     find the bits in which they differ (OR ^ AND over all keys);
+//  2. insert each key into an LDS hash table keyed by the index of its first
+//     occurrence (whose staged key is compared), counting duplicates;
+//  3. read the distinct keys and counts out of the table into registers and
+//     partition them by the 8 bits below the highest differing bit (whole
+//     workgroup) into their final buffer, then finish each piece: up to SMALL
+//     keys by one lane's sorting network, up to 64 by one wave ranking each key
+//     against the others, larger ones by a wave partition on their next 8 bits;
 //  4. write the sorted distinct keys and their counts over the batch's first
 //     positions and mark those positions in the bitmap.
 // Bits [off, off + nu) of the bitmap set, the rest of [off, off + m) left
@@ -979,7 +992,6 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
   using Cfg = LocalCfg<K>;
   constexpr int NT = Cfg::NT, NW = NT / 64, SLOTS = Cfg::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
-  constexpr int SPT = (SLOTS + NT - 1) / NT;
   constexpr int LPT = (LocalCfg<K>::CAP + NT - 1) / NT;  // keys per thread
   __shared__ LocalLds<K> s;
   if (ctl->status) return;
@@ -998,6 +1010,8 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
       pre[j] = e < b.size ? src[b.off + e] : K(0);
     }
   };
+  if (tid == 0) s.dirty = 1;  // the table starts uninitialised
+  __syncthreads();
   const Batch none = {0, 0, 0};
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
   prefetch(nxt);
@@ -1005,31 +1019,48 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
   for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
     const Batch bt = nxt;
     const uint32_t m = bt.size;
-    // 1. stage and hash
+    // 1. stage (and find the bits in which the batch's keys differ: OR ^ AND)
+    K kor = 0, kand = all_ones<K>();
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
       const uint32_t e = tid + (uint32_t)j * NT;
-      if (e < m) s.key0[e] = pre[j];
+      if (e < m) {
+        s.key0[e] = pre[j];
+        kor |= pre[j];
+        kand &= pre[j];
+      }
+    }
+    kor = wave_or_key(kor);
+    kand = wave_and_key(kand);
+    if (lane == 0) {
+      s.wor[w] = kor;
+      s.wand[w] = kand;
     }
     nxt = nxt2;
     nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
     if (bi + G < n_batches) prefetch(nxt);
-    for (uint32_t q = tid; q < (uint32_t)SLOTS; q += NT) {
-      own[q] = EMPTY;
-      tcnt[q] = 0;
+    if (s.dirty) {  // uniform: read after the previous batch's final barrier
+      for (uint32_t q = tid; q < (uint32_t)SLOTS; q += NT) {
+        own[q] = EMPTY;
+        tcnt[q] = 0;
+      }
     }
+    __syncthreads();
     if (tid == 0) {
       s.nlarge[0] = s.nlarge[1] = 0;
       s.nmid = 0;
+      s.nuniq = 0;
+      s.dirty = 0;
     }
+    if (tid < 256) s.hist[0][tid] = 0;
     __syncthreads();
+    // 2. count duplicates in an LDS hash table keyed by the first occurrence
     {
       // first probe of every key of this thread at once (independent LDS
       // atomics in flight), then linear probing for the few that collided
-      constexpr int KPT = (LocalCfg<K>::CAP + NT - 1) / NT;
-      uint32_t hs[KPT], os[KPT];
+      uint32_t hs[LPT], os[LPT];
 #pragma unroll
-      for (int j = 0; j < KPT; ++j) {
+      for (int j = 0; j < LPT; ++j) {
         const uint32_t e = tid + (uint32_t)j * NT;
         hs[j] = 0;
         os[j] = EMPTY;
@@ -1039,76 +1070,77 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
         }
       }
 #pragma unroll
-      for (int j = 0; j < KPT; ++j) {
+      for (int j = 0; j < LPT; ++j) {
         const uint32_t e = tid + (uint32_t)j * NT;
+        bool claimed = false;
+        uint32_t h = hs[j];
         if (e < m) {
           const K key = s.key0[e];
-          uint32_t h = hs[j], o = os[j];
+          uint32_t o = os[j];
           while (o != EMPTY && s.key0[o] != key) {
             h = h + 1 == (uint32_t)SLOTS ? 0u : h + 1;
             o = atomicCAS(&own[h], EMPTY, e);
           }
+          claimed = o == EMPTY;
           atomicAdd(&tcnt[h], 1u);
+        }
+        // the lane that claimed a slot records it: one LDS atomic per wave
+        const uint64_t cm = __ballot(claimed);
+        if (cm) {
+          uint32_t base = 0;
+          if (lane == (uint32_t)(__ffsll((long long)cm) - 1))
+            base = atomicAdd(&s.nuniq, (uint32_t)__popcll(cm));
+          base = __shfl(base, __ffsll((long long)cm) - 1, 64);
+          if (claimed) s.ulist[base + (uint32_t)__popcll(cm & lanemask_lt())] = (uint16_t)h;
         }
       }
     }
     __syncthreads();
-    // 2. compact: thread t owns slots [t*SPT, (t+1)*SPT)
-    K uk[SPT];
-    uint32_t uc[SPT];
-    uint32_t nv = 0;
+    K kall_or = 0, kall_and = all_ones<K>();
 #pragma unroll
-    for (int j = 0; j < SPT; ++j) {
-      const uint32_t q = tid * SPT + j;
-      const uint32_t o = q < (uint32_t)SLOTS ? own[q] : EMPTY;
-      uc[j] = o != EMPTY ? tcnt[q] : 0u;
-      uk[j] = o != EMPTY ? s.key0[o] : K(0);
-      nv += o != EMPTY ? 1u : 0u;
+    for (int i = 0; i < NW; ++i) {
+      kall_or |= s.wor[i];
+      kall_and &= s.wand[i];
     }
-    uint32_t nu;
-    uint32_t pos = block_exclusive_scan<NT>(nv, s.wsum, &nu);
-    // (the scan's barriers separate the reads above from the writes below)
-    K diff = 0;
+    const int hb = bit_length(kall_or ^ kall_and);
+    // 3. distinct keys (read from the table into registers through the list of
+    //    claimed slots) partitioned by the 8 bits below hb straight into buffer 0
+    const uint32_t nu = s.nuniq;
+    constexpr int UPT = (LocalCfg<K>::CAP + NT - 1) / NT;
+    K uk[UPT];
+    uint32_t uc[UPT], ud[UPT];
 #pragma unroll
-    for (int j = 0; j < SPT; ++j)
+    for (int j = 0; j < UPT; ++j) {
+      const uint32_t u = tid + (uint32_t)j * NT;
+      uc[j] = 0;
+      ud[j] = 0;
+      uk[j] = K(0);
+      if (u < nu) {
+        const uint32_t q = s.ulist[u];
+        uk[j] = s.key0[own[q]];
+        uc[j] = tcnt[q];
+        ud[j] = hb > 0 ? seg_digit(uk[j], hb) : 0u;
+        atomicAdd(&s.hist[0][ud[j]], 1u);
+        own[q] = EMPTY;  // leave the table clean for the next batch
+        tcnt[q] = 0;
+      }
+    }
+    __syncthreads();
+    const uint32_t c = tid < 256 ? s.hist[0][tid] : 0u;
+    uint32_t tot;
+    const uint32_t st = block_exclusive_scan<NT>(c, s.wsum, &tot);
+    if (tid < 256) s.hist[0][tid] = st;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < UPT; ++j)
       if (uc[j]) {
-        s.key0[pos] = uk[j];
-        s.cnt0[pos] = uc[j];
-        ++pos;
+        const uint32_t q = atomicAdd(&s.hist[0][ud[j]], 1u);
+        s.key0[q] = uk[j];
+        s.cnt0[q] = (uint16_t)uc[j];
       }
     __syncthreads();
-    // highest differing bit among the distinct keys
-    const K k0 = s.key0[0];
-    for (uint32_t u = tid; u < nu; u += NT) diff |= s.key0[u] ^ k0;
-    diff = wave_or_key(diff);
-    if (lane == 0) s.wor[w] = diff;
-    if (tid < 256) s.hist[0][tid] = 0;
-    __syncthreads();
-    K all = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) all |= s.wor[i];
-    const int hb = bit_length(all);
     int cur = 0;
-    if (hb > 0) {
-      // 3. whole-workgroup partition of the distinct keys into buffer 1
-      K *k1 = s.key1();
-      uint32_t *c1 = s.cnt1();
-      for (uint32_t u = tid; u < nu; u += NT) atomicAdd(&s.hist[0][seg_digit(s.key0[u], hb)], 1u);
-      __syncthreads();
-      const uint32_t c = tid < 256 ? s.hist[0][tid] : 0u;
-      uint32_t tot;
-      const uint32_t st = block_exclusive_scan<NT>(c, s.wsum, &tot);
-      if (tid < 256) s.hist[0][tid] = st;
-      __syncthreads();
-      for (uint32_t u = tid; u < nu; u += NT) {
-        const K key = s.key0[u];
-        const uint32_t q = atomicAdd(&s.hist[0][seg_digit(key, hb)], 1u);
-        k1[q] = key;
-        c1[q] = s.cnt0[u];
-      }
-      __syncthreads();
-      if (tid < 256) classify_segment<K>(s, st, c, hb - 8, 1u, 0);
-    }
+    if (tid < 256) classify_segment<K>(s, st, c, hb > 0 ? hb - 8 : 0, 0u, 0);
     while (true) {
       __syncthreads();
       // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
@@ -1116,7 +1148,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
         const uint64_t d = s.mid[i];
         const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
         const K *kb = s.keys_of(buf);
-        const uint32_t *cb = s.cnts_of(buf);
+        const uint16_t *cb = s.cnts_of(buf);
         {
           const uint32_t me = lane;
           const K x = me < c ? kb[st + me] : all_ones<K>();
@@ -1128,7 +1160,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
           // operations of one wave complete in order)
           if (me < c) {
             s.key0[st + rank] = x;
-            s.cnt0[st + rank] = xc;
+            s.cnt0[st + rank] = (uint16_t)xc;
           }
         }
       }
@@ -1143,9 +1175,10 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
         const uint64_t d = s.large[cur][i];
         const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
         const K *ik = s.keys_of(buf);
-        const uint32_t *ic = s.cnts_of(buf);
+        const uint16_t *ic = s.cnts_of(buf);
         K *ok = s.keys_of(buf ^ 1u);
-        uint32_t *oc = s.cnts_of(buf ^ 1u);
+        uint16_t *oc = s.cnts_of(buf ^ 1u);
+        if (buf == 0 && lane == 0) s.dirty = 1;  // buffer 1 overwrites the hash table
         uint32_t *h = s.hist[w];
         K dd = 0;
         const K kk = ik[st];
@@ -1184,7 +1217,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
     //    bitmap marks those positions
     for (uint32_t u = tid; u < nu; u += NT) {
       b0[bt.off + u] = s.key0[u];
-      b1[bt.off + u] = (K)s.cnt0[u];
+      b1[bt.off + u] = (K)(uint32_t)s.cnt0[u];
     }
     mark_positions(bits, bt.off, m, nu);
     __syncthreads();
