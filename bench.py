@@ -37,7 +37,7 @@ def log(msg):
 
 def stage_names():
     return ["start", "offsets", "enum_hist", "plan", "enum_scatter", "levels", "local_sort",
-            "rle_count", "rle_write", "end"]
+            "emit_count", "emit_write", "end"]
 
 
 def algorithmic_bytes(stage, n_keys, n_unique, n_bases, n_reads, w, row_bytes):
@@ -47,10 +47,10 @@ def algorithmic_bytes(stage, n_keys, n_unique, n_bases, n_reads, w, row_bytes):
         return n_bases / 4 + 16 * n_reads
     if stage == "enum_scatter":
         return n_bases / 4 + 16 * n_reads + n_keys * w
-    if stage == "local_sort":
-        return 2 * n_keys * w
-    if stage == "rle_write":
-        return n_keys * w + n_unique * (row_bytes + 8)
+    if stage == "local_sort":  # keys in; distinct keys + counts and the run bitmap out
+        return n_keys * w + 2 * n_unique * w + n_keys / 8
+    if stage == "emit_write":  # distinct keys + counts and the bitmap in; table rows out
+        return 2 * n_unique * w + n_keys / 8 + n_unique * row_bytes
     return None
 
 
@@ -160,7 +160,7 @@ def main():
     log("stages (ms): " + ", ".join(f"{k_}={v:.3f}" for k_, v in stages.items()))
 
     # dominant single-kernel stage and its roofline
-    row_bytes = {"edges": 2 * w + 1 + 4 + w, "nodes": w + 4}
+    row_bytes = {"edges": 3 * w + 5, "nodes": w + 4}
     uniq = {"edges": n_edges, "nodes": n_nodes}
     keys = {"edges": n_e, "nodes": n_k}
     best = None
@@ -175,10 +175,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "ms": round(kms, 4)}
 
-    # sort + reduce share of the build: partition levels, LDS sort, run-length reduce
+    # sort + reduce share of the build: partitions, LDS sort, emission of the tables
     sr_ms = sum(v for n_, v in stages.items()
-                if n_.split(".")[1] in ("enum_scatter", "levels", "local_sort", "rle_count",
-                                         "rle_write"))
+                if n_.split(".")[1] in ("enum_scatter", "levels", "local_sort", "emit_count",
+                                         "emit_write"))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
