@@ -74,6 +74,86 @@ def run_cpu_baseline(rs, k, target_s=15.0):
                       f"{dt:.1f} s wall"}
 
 
+def run_batched(args):
+    """256 independent read sets (batched-build workload): one dbg_build_batched
+    launch sequence against 256 sequential dbg_build calls on the same stream."""
+    import torch
+    from paper_1003_1940_amd import api, synth
+    k = 31
+    log(f"generating {args.n_sets} read sets (scale {args.scale})")
+    sets = synth.batched_sets(n_sets=args.n_sets, scale=args.scale)
+    bases = np.concatenate([s.bases for s in sets])
+    lens = np.concatenate([np.diff(s.offsets.astype(np.int64)) for s in sets])
+    offsets = np.zeros(len(lens) + 1, np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    sro = np.zeros(len(sets) + 1, np.uint64)
+    np.cumsum([s.n_reads for s in sets], out=sro[1:])
+    set_kmers = [s.kmer_count(k) for s in sets]
+    n_k = int(sum(set_kmers))
+    log(f"{len(sets)} sets, {len(lens)} reads, {int(offsets[-1])} bases, {n_k} k-mers")
+    dev = torch.device("cuda", 0)
+    packed, offs, n_bases = api.upload(bases, offsets, dev)
+    sets_d = torch.from_numpy(sro.view(np.int64).copy()).to(dev)
+    out = api.alloc_outputs(k, n_k, n_k, dev, zkey=True)
+    ws = api.Workspace(len(lens), len(sets), n_k, k, dev)
+    nso = torch.zeros(len(sets) + 1, dtype=torch.int64, device=dev)
+    eso = torch.zeros(len(sets) + 1, dtype=torch.int64, device=dev)
+    res = torch.zeros(3, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        api.build_async(packed, n_bases, offs, k, n_k, out, n_k, n_k, res, ws, stream,
+                        set_offsets=sets_d, node_set_offsets=nso, edge_set_offsets=eso)
+
+    # plain per-set builds: each set's reads are a slice of the same device stream
+    per = []
+    max_keys = max(set_kmers)
+    max_reads = max(s.n_reads for s in sets)
+    ws1 = api.Workspace(max_reads, 1, max_keys, k, dev)
+    out1 = api.alloc_outputs(k, max_keys, max_keys, dev, zkey=True)
+    res1 = torch.zeros(3, dtype=torch.int64, device=dev)
+    set_offs, set_packed = [], []
+    for i, srs in enumerate(sets):
+        p, o, nb = api.upload(srs.bases, srs.offsets, dev)
+        set_packed.append((p, o, nb))
+
+    def plain_all():
+        for (p, o, nb), kk in zip(set_packed, set_kmers):
+            api.build_async(p, nb, o, k, kk, out1, kk, kk, res1, ws1, stream)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    log("timing batched")
+    t_b = timed(batched, args.steps, args.warmup)
+    n_nodes, n_edges, status = api.read_result(res)
+    if status:
+        raise SystemExit(f"device status {status}: {api.strerror(status)}")
+    log("timing plain per-set builds")
+    t_p = timed(plain_all, max(1, args.steps // 4), 1)
+    line = {
+        "metric": "k-mers/s into bi-directed graph (batched build)",
+        "value": n_k / (t_b / 1e3), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batched_k31", "sets": len(sets), "reads": int(len(lens)),
+                   "kmers": n_k, "nodes": n_nodes, "edges": n_edges, "scale": args.scale},
+        "plain_per_set": {"ms_for_all_sets": t_p, "value": n_k / (t_p / 1e3),
+                          "unit": "k-mers/s"},
+        "batched_over_plain": t_p / t_b,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +162,9 @@ def main():
     ap.add_argument("--workload", default="plain_repeats_k31", choices=sorted(WORKLOADS))
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="the batched-build workload (many read sets in one launch sequence)")
+    ap.add_argument("--n-sets", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -89,8 +172,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.batched:
+        run_batched(args)
+        return
+
     import torch
-    import paper_1003_1940_amd as dbg
     from paper_1003_1940_amd import api, synth
 
     gen_name, k = WORKLOADS[args.workload]

@@ -539,8 +539,10 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
                                          tr.end, tr.read_lo, tr.read_hi, keys);
   const uint64_t t_first = a.set_tbase[tr.set];
   const uint32_t d = threadIdx.x;
-  const uint64_t base = cursor0[(uint64_t)tr.set * 256 + d] + tpre[t * 256 + d] -
-                        tpre[t_first * 256 + d];
+  // tile prefixes are counted modulo 2^32; a difference is exact because a table
+  // holds fewer than 2^32 keys
+  const uint64_t base = cursor0[(uint64_t)tr.set * 256 + d] +
+                        (uint32_t)(tpre[t * 256 + d] - tpre[t_first * 256 + d]);
   partition_tile<K>(keys, n, a.bits, 0, nullptr, base, dst, s);
 }
 
@@ -652,7 +654,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_set_plan(PlanArgs p, const uint32
   if (p.ctl->status) return;
   const uint32_t d = threadIdx.x;
   for (uint64_t s = blockIdx.x; s < n_sets; s += gridDim.x) {
-    const uint64_t c = (uint64_t)tpre[set_tbase[s + 1] * 256 + d] - tpre[set_tbase[s] * 256 + d];
+    const uint64_t c = (uint32_t)(tpre[set_tbase[s + 1] * 256 + d] - tpre[set_tbase[s] * 256 + d]);
     plan_children(p, c, set_kbase[s], 0, 1, cursor0 + s * 256, lds);
   }
 }

@@ -56,8 +56,12 @@ class ReadSet:
 
 def random_genome(rng: np.random.Generator, size: int, gc: float = 0.5) -> np.ndarray:
     """i.i.d. base codes 0..3 (A, C, G, T) with P(C) = P(G) = gc / 2."""
-    p = np.array([(1 - gc) / 2, gc / 2, gc / 2, (1 - gc) / 2])
-    return rng.choice(4, size=size, p=p).astype(np.uint8)
+    if gc == 0.5:
+        return rng.integers(0, 4, size=size, dtype=np.uint8)
+    # C or G with probability gc, then which of the pair with probability 1/2
+    strong = rng.random(size) < gc
+    pick = rng.integers(0, 2, size=size, dtype=np.uint8)
+    return np.where(strong, 1 + pick, 3 * pick).astype(np.uint8)
 
 
 def insert_repeats(rng: np.random.Generator, genome: np.ndarray, copies: int, length: int) -> None:
@@ -70,7 +74,7 @@ def insert_repeats(rng: np.random.Generator, genome: np.ndarray, copies: int, le
 
 
 def sample_reads(rng: np.random.Generator, genome: np.ndarray, n_reads: int, read_len,
-                 err: float, p_rc: float = 0.5, chunk: int = 1 << 20) -> ReadSet:
+                 err: float, p_rc: float = 0.5, chunk: int = 1 << 16) -> ReadSet:
     """Reads of length ``read_len`` (an int, or an array of per-read lengths)."""
     lens = (np.full(n_reads, int(read_len), np.int64) if np.isscalar(read_len)
             else np.asarray(read_len, np.int64))
@@ -87,12 +91,34 @@ def sample_reads(rng: np.random.Generator, genome: np.ndarray, n_reads: int, rea
             flip = rng.random(len(sel)) < p_rc
             codes[flip] = 3 - codes[flip, ::-1]
             if err > 0:
-                hit = rng.random(codes.shape) < err
-                codes[hit] = (codes[hit] + rng.integers(1, 4, size=int(hit.sum()),
-                                                         dtype=np.uint8)) & 3
-            rows = offsets[sel].astype(np.int64)
-            out[rows[:, None] + np.arange(L)[None, :]] = ALPHABET[codes]
+                flat = codes.reshape(-1)
+                hit = bernoulli_positions(rng, flat.size, err)
+                flat[hit] = (flat[hit] + rng.integers(1, 4, size=hit.size, dtype=np.uint8)) & 3
+            letters = ALPHABET[codes]
+            if len(sel) == c1 - c0:
+                # every read of the chunk has this length: its rows are one slice
+                out[int(offsets[c0]):int(offsets[c1])] = letters.reshape(-1)
+            else:
+                rows = offsets[sel].astype(np.int64)
+                out[rows[:, None] + np.arange(L)[None, :]] = letters
     return ReadSet(out, offsets)
+
+
+def bernoulli_positions(rng: np.random.Generator, n: int, p: float) -> np.ndarray:
+    """Indices in [0, n) each chosen independently with probability p, in increasing
+    order.  The gaps between successive chosen indices of a Bernoulli(p) sequence are
+    i.i.d. geometric(p), so the positions are the running sums of geometric draws."""
+    if n == 0 or p <= 0:
+        return np.zeros(0, np.int64)
+    parts, pos = [], -1
+    want = int(n * p + 6 * math.sqrt(n * p) + 16)
+    while pos < n:
+        gaps = rng.geometric(p, size=want)
+        at = pos + np.cumsum(gaps)
+        parts.append(at)
+        pos = int(at[-1])
+    at = np.concatenate(parts)
+    return at[at < n]
 
 
 def from_strings(reads) -> ReadSet:

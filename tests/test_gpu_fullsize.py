@@ -1,0 +1,66 @@
+"""Full-size checks at the benchmark configuration: the 2,000,000-read k = 31
+workload, built exactly as bench.py builds it.  The oracle cannot hold the whole
+graph, so (1) every output row is checked against the invariants that hold at
+any size, and (2) sampled rows, and sampled keys that must be absent, are counted
+by the oracle's probe scan over all reads."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1003_1940_amd import synth
+from . import keys_np as K
+from .gpu_util import gpu_graph, say
+from .invariants import check_graph
+
+pytestmark = pytest.mark.gpu
+
+
+class _G:
+    def __init__(self, d):
+        self.__dict__.update(d)
+
+
+@pytest.fixture(scope="module")
+def repeats_full():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the GPU tests need the MI355X")
+    oracle.build(force=False)
+    say("[gpu-fullsize] generating the 2,000,000-read k=31 workload")
+    rs = synth.plain_repeats()
+    say("[gpu-fullsize] building on the GPU")
+    g, got = gpu_graph(rs.bases, rs.offsets, 31)
+    assert g.status == 0
+    return rs, g, got
+
+
+def test_fullsize_invariants(repeats_full):
+    rs, g, got = repeats_full
+    say(f"[gpu-fullsize] invariants over {g.n_nodes} nodes, {g.n_edges} edges")
+    check_graph(_G(got), 31, rs.bases, rs.offsets)
+
+
+def test_fullsize_sampled_counts(repeats_full):
+    rs, g, got = repeats_full
+    rng = np.random.default_rng(2024)
+    k = 31
+    ni = np.sort(rng.choice(len(got["node_count"]), size=400, replace=False))
+    ei = np.sort(rng.choice(len(got["edge_mult"]), size=400, replace=False))
+    node_probes = [K.to_str(got["node_key"][i, 0], got["node_key"][i, 1], k) for i in ni]
+    # keys absent from the table: random canonical k-mers that are not nodes
+    absent = []
+    nodes = got["node_key"][:, 0]
+    while len(absent) < 40:
+        lo = rng.integers(0, 1 << 62, dtype=np.uint64)
+        clo, chi, _ = K.canonical(np.array([lo], np.uint64), np.array([0], np.uint64), k)
+        i = np.searchsorted(nodes, clo[0])
+        if i >= len(nodes) or nodes[i] != clo[0]:
+            absent.append(K.to_str(clo[0], 0, k))
+    edge_probes = [(K.to_str(got["edge_u"][i, 0], 0, k), K.to_str(got["edge_v"][i, 0], 0, k),
+                    int(got["edge_orient"][i])) for i in ei]
+    say("[gpu-fullsize] oracle probe scan over all reads")
+    nc, ec = oracle.probe_counts(rs.bases, rs.offsets, k, node_probes + absent, edge_probes)
+    assert np.array_equal(nc[:len(ni)], got["node_count"][ni]), "sampled node counts differ"
+    assert (nc[len(ni):] == 0).all(), "a key absent from the node table occurs in the reads"
+    assert np.array_equal(ec, got["edge_mult"][ei]), "sampled edge multiplicities differ"
