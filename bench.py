@@ -54,6 +54,57 @@ def algorithmic_bytes(stage, n_keys, n_unique, n_bases, n_reads, w, row_bytes):
     return None
 
 
+KERNEL_SOURCES = ("paper_1003_1940_amd/csrc/dbg_kernels.hip",
+                  "paper_1003_1940_amd/csrc/dbg_device.h",
+                  "paper_1003_1940_amd/csrc/dbg_internal.h")
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources: counter readings taken on other sources are
+    not reported as this build's traffic."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` ("edges.local_sort", ...) from the counter
+    summary profiles/hbm_traffic_<workload>.md: FETCH_SIZE and WRITE_SIZE per
+    dispatch, each scaled by the factor a plain copy of known size gave.  None if
+    there is no summary, it lacks the kernel, or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    a = text.find("```json")
+    if a < 0:
+        return None
+    b = text.find("```", a + 7)
+    data = json.loads(text[a + 7:b])
+    if data.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    row = data.get("kernels", {}).get(kernel)
+    if row is None:
+        return None
+    return row["fetch_kib"] * 1024 * data["fetch_scale"] + row["write_kib"] * 1024 * data["write_scale"]
+
+
+def run_copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size, for scaling the HBM counters."""
+    import torch
+    dev = torch.device("cuda", 0)
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(7)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def run_cpu_baseline(rs, k, target_s=15.0):
     """The oracle, as is, on a bounded prefix of the reads (host cores)."""
     import oracle
@@ -165,6 +216,8 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="the batched-build workload (many read sets in one launch sequence)")
     ap.add_argument("--n-sets", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -172,6 +225,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        run_copy_calibration()
+        return
     if args.batched:
         run_batched(args)
         return
@@ -257,14 +313,29 @@ def main():
             best = (name, t, b)
     kname, kms, kbytes = best
     achieved = kbytes / (kms / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, kname) if args.scale == 1.0 else None
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "ms": round(kms, 4)}
+                "traffic": None if traffic is None else round(traffic),
+                "algorithmic_bytes": round(kbytes), "ms": round(kms, 4)}
 
     # sort + reduce share of the build: partitions, LDS sort, emission of the tables
     sr_ms = sum(v for n_, v in stages.items()
                 if n_.split(".")[1] in ("enum_scatter", "levels", "local_sort", "emit_count",
                                          "emit_write"))
+    # The same build priced as the 8-bit LSD formulation would move it: per key and
+    # table, one enumeration write, one histogram read, a read and a write per digit
+    # pass, one run-length read; per distinct key a key and a count written; per
+    # distinct edge the decode read and its row written.
+    def lsd_bytes(n, u, bits):
+        passes = (bits + 7) // 8
+        return n * w * (1 + 1 + 2 * passes + 1) + u * (w + 4)
+    lsd = (lsd_bytes(n_e, n_edges, 2 * k + 2) + n_edges * (w + 4) + n_edges * (2 * w + 5)
+           + lsd_bytes(n_k, n_nodes, 2 * k))
+    lsd_gbs = lsd / (ms / 1e3) / 1e9
+    build_lsd = {"bytes": round(lsd), "achieved": round(lsd_gbs, 1), "unit": "GB/s",
+                 "frac": round(lsd_gbs / HBM_PEAK_GBS, 4)}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
@@ -286,6 +357,7 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms": {k_: round(v, 4) for k_, v in stages.items()},
         "sort_reduce_ms": round(sr_ms, 4),
+        "build_as_lsd_d8": build_lsd,
         "h2d_upload_and_pack_s": round(h2d_s, 4),
     }
     print(json.dumps(line), flush=True)
