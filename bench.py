@@ -132,7 +132,8 @@ def run_batched(args):
     from paper_1003_1940_amd import api, synth
     k = 31
     log(f"generating {args.n_sets} read sets (scale {args.scale})")
-    sets = synth.batched_sets(n_sets=args.n_sets, scale=args.scale)
+    sets = synth.batched_sets(n_sets=args.n_sets, scale=args.scale,
+                              workers=max(1, min(16, os.cpu_count() or 1)))
     bases = np.concatenate([s.bases for s in sets])
     lens = np.concatenate([np.diff(s.offsets.astype(np.int64)) for s in sets])
     offsets = np.zeros(len(lens) + 1, np.uint64)
@@ -205,6 +206,61 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def run_served(args):
+    """Served-build workload: a Poisson stream of requests (mean 200/s; read sets
+    from a pool of 256, k of 31 or 63) served by the continuous-batching loop and by
+    a first-in first-out loop of single builds, on the same trace; then the same
+    requests all at once, for the throughput each loop sustains."""
+    import torch
+    from paper_1003_1940_amd import synth
+    from paper_1003_1940_amd.serve import Request, Server, pin_read_set, summarize
+    n_req = args.requests + args.warmup_requests
+    workers = max(1, min(16, os.cpu_count() or 1))
+    log(f"generating the request pool (256 sets, {workers} workers) and {n_req} arrivals")
+    arrivals, which, ks, pool = synth.served_trace(n_req, rate=args.rate, pool_size=256,
+                                                   scale=args.scale, workers=workers)
+    log(f"pool: {sum(p.n_bases for p in pool)} bases; pinning")
+    pinned = [pin_read_set(p.bases, p.offsets) for p in pool]
+    del pool
+
+    def trace(burst):
+        return [Request(i, pinned[w][0], pinned[w][1], int(k), 0.0 if burst else float(a))
+                for i, (a, w, k) in enumerate(zip(arrivals, which, ks))]
+
+    out = {}
+    for name, slots in (("continuous", args.slots), ("fifo", 1)):
+        for burst in (False, True):
+            reqs = trace(burst)
+            log(f"{name} ({slots} slots), {'all at once' if burst else 'Poisson arrivals'}")
+            st = Server(slots=slots).run(reqs)
+            summ = summarize(reqs, skip=0 if burst else args.warmup_requests)
+            summ.update(mean_inflight=round(st["mean_inflight"], 2),
+                        peak_inflight=st["peak_inflight"])
+            out[f"{name}_{'burst' if burst else 'poisson'}"] = summ
+            log(f"  {summ}")
+            del reqs
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    c, f = out["continuous_poisson"], out["fifo_poisson"]
+    line = {
+        "metric": "k-mers/s into bi-directed graph (served build)",
+        "value": c["kmers_per_s"], "unit": "k-mers/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": args.warmup_requests,
+        "ms_per_step": c["span_s"] * 1e3 / max(1, c["requests"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64+u128", "data": "synthetic",
+        "config": {"workload": "served_poisson", "rate_per_s": args.rate, "pool": 256,
+                   "requests": args.requests, "warmup_requests": args.warmup_requests,
+                   "slots": args.slots, "scale": args.scale},
+        "latency_ms": {"p50": c["p50_ms"], "p99": c["p99_ms"]},
+        "fifo": {"p50_ms": f["p50_ms"], "p99_ms": f["p99_ms"], "kmers_per_s": f["kmers_per_s"]},
+        "saturated_kmers_per_s": {"continuous": out["continuous_burst"]["kmers_per_s"],
+                                  "fifo": out["fifo_burst"]["kmers_per_s"]},
+        "modes": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +272,12 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="the batched-build workload (many read sets in one launch sequence)")
     ap.add_argument("--n-sets", type=int, default=256)
+    ap.add_argument("--served", action="store_true",
+                    help="the served-build workload (Poisson request stream)")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--warmup-requests", type=int, default=100)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -230,6 +292,9 @@ def main():
         return
     if args.batched:
         run_batched(args)
+        return
+    if args.served:
+        run_served(args)
         return
 
     import torch

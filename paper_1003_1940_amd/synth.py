@@ -173,41 +173,61 @@ def plain_large(scale: float = 1.0) -> ReadSet:
     return rs
 
 
-def batched_sets(n_sets: int = 256, scale: float = 1.0) -> list:
+def _map(fn, args, workers: int):
+    """fn over args in order; with workers > 1 in forked processes (each item
+    draws from its own seed, so the result does not depend on the split).  Fork
+    before the process touches a GPU."""
+    if workers <= 1 or len(args) <= 1:
+        return [fn(a) for a in args]
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    ctx = multiprocessing.get_context("fork")
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        return list(ex.map(fn, args, chunksize=1))
+
+
+def _batched_set(arg):
+    child, scale = arg
+    rng = np.random.default_rng(child)
+    G = int(round(math.exp(rng.uniform(math.log(2e4), math.log(2e6)))))
+    cov = rng.uniform(10, 50)
+    g = random_genome(rng, G)
+    n = max(1, int(round(G * cov / 100 * scale)))
+    rs = sample_reads(rng, g, n, 100, 0.01)
+    rs.params = dict(genome=G, coverage=cov, reads=n)
+    return rs
+
+
+def batched_sets(n_sets: int = 256, scale: float = 1.0, workers: int = 1) -> list:
     """Batched build, k = 31: independent read sets, each from its own genome of
     size log-uniform in [20,000, 2,000,000]; reads of length 100 at coverage
     uniform in [10x, 50x], strand p = 0.5, 1% errors."""
     root = np.random.SeedSequence(SEED_BASE + 3)
-    out = []
-    for child in root.spawn(n_sets):
-        rng = np.random.default_rng(child)
-        G = int(round(math.exp(rng.uniform(math.log(2e4), math.log(2e6)))))
-        cov = rng.uniform(10, 50)
-        g = random_genome(rng, G)
-        n = max(1, int(round(G * cov / 100 * scale)))
-        rs = sample_reads(rng, g, n, 100, 0.01)
-        rs.params = dict(genome=G, coverage=cov, reads=n)
-        out.append(rs)
-    return out
+    return _map(_batched_set, [(c, scale) for c in root.spawn(n_sets)], workers)
+
+
+def _pool_set(arg):
+    child, scale = arg
+    prng = np.random.default_rng(child)
+    G = int(round(math.exp(prng.uniform(math.log(1e4), math.log(5e6)) + math.log(scale))))
+    G = max(G, 1000)
+    L = int(prng.choice([100, 150]))
+    n = max(1, int(round(G * 30 / L)))
+    rs = sample_reads(prng, random_genome(prng, G), n, L, 0.01)
+    rs.params = dict(genome=G, read_len=L, reads=n)
+    return rs
 
 
 def served_trace(n_requests: int, rate: float = 200.0, pool_size: int = 256,
-                 scale: float = 1.0):
+                 scale: float = 1.0, workers: int = 1):
     """Served build: Poisson arrivals (mean ``rate`` per second) of requests whose
     read sets come from a pool of ``pool_size`` sets: genome size log-uniform in
-    [10,000, 5,000,000], read length 100 or 150, coverage 30x, 1% errors, k drawn
-    from {31, 63}.  Returns (arrival_times_s, pool_index, k_per_request, pool)."""
+    [10,000, 5,000,000] (times ``scale``), read length 100 or 150, coverage 30x,
+    1% errors, k drawn from {31, 63}.  Returns (arrival_times_s, pool_index,
+    k_per_request, pool)."""
     rng = np.random.default_rng(SEED_BASE + 4)
-    pool = []
-    for child in np.random.SeedSequence(SEED_BASE + 40).spawn(pool_size):
-        prng = np.random.default_rng(child)
-        G = int(round(math.exp(prng.uniform(math.log(1e4), math.log(5e6)) + math.log(scale))))
-        G = max(G, 1000)
-        L = int(prng.choice([100, 150]))
-        n = max(1, int(round(G * 30 / L)))
-        rs = sample_reads(prng, random_genome(prng, G), n, L, 0.01)
-        rs.params = dict(genome=G, read_len=L, reads=n)
-        pool.append(rs)
+    children = np.random.SeedSequence(SEED_BASE + 40).spawn(pool_size)
+    pool = _map(_pool_set, [(c, scale) for c in children], workers)
     gaps = rng.exponential(1.0 / rate, size=n_requests)
     arrivals = np.cumsum(gaps)
     which = rng.integers(0, pool_size, size=n_requests)
