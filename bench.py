@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--warmup-requests", type=int, default=100)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--node-route", choices=("auto", "kmers", "endpoints"), default="auto",
+                    help="how the node table is built (default: the library's choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -300,6 +302,9 @@ def main():
     import torch
     from paper_1003_1940_amd import api, synth
 
+    if args.node_route != "auto":
+        api.set_tuning(node_path={"kmers": api.NODES_KMERS,
+                                  "endpoints": api.NODES_ENDPOINTS}[args.node_route])
     gen_name, k = WORKLOADS[args.workload]
     log(f"generating {args.workload} (scale {args.scale})")
     rs = getattr(synth, gen_name)(scale=args.scale)
@@ -357,6 +362,8 @@ def main():
     n_nodes, n_edges, status = api.read_result(result)
     if status != 0:
         raise SystemExit(f"device status {status}: {api.strerror(status)}")
+    node_route = ("endpoints" if api.read_flags(result) & api.FLAG_NODES_FROM_ENDPOINTS
+                  else "kmers")
 
     names = stage_names()
     stages = {}
@@ -417,7 +424,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "reads": n_reads, "read_len": rs.params.get("read_len"),
                    "k": k, "genome": rs.params.get("genome"), "kmers": n_k, "kplus1mers": n_e,
-                   "nodes": n_nodes, "edges": n_edges, "scale": args.scale},
+                   "nodes": n_nodes, "edges": n_edges, "scale": args.scale,
+                   "node_route": node_route},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms": {k_: round(v, 4) for k_, v in stages.items()},

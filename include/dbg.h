@@ -107,8 +107,12 @@ typedef struct {
   uint64_t n_nodes; /* distinct canonical k-mers (true count, even beyond capacity) */
   uint64_t n_edges; /* distinct canonical edges */
   uint32_t status;  /* DBG_OK or the first device-side error */
-  uint32_t reserved;
+  uint32_t flags;   /* DBG_FLAG_* bits describing how the build ran */
 } dbg_result_t;
+
+/* dbg_result_t.flags: the node table was built from the edge endpoints (see
+ * dbg_tuning_t) rather than from the enumerated k-mers. */
+#define DBG_FLAG_NODES_FROM_ENDPOINTS 1u
 
 /* Bytes of device workspace a build needs.  n_reads, n_sets as passed to the
  * build; max_keys is an upper bound on the number of k-mer positions
@@ -166,6 +170,41 @@ int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
  * single-stream benchmarking; pass NULL to stop recording. */
 #define DBG_STAGE_EVENTS 20
 int dbg_set_stage_events(hipEvent_t *events, int n_events);
+
+/* How the node table is built.  STEP-3 of Sec. 3 gives the node set as the
+ * endpoints of the distinct edges; with counts this is: every k-mer occurrence
+ * is the first k-mer or the last k-mer of a (k+1)-mer occurrence, or both ends
+ * of a read, so twice a node's count equals the sum, over the distinct edges,
+ * of the edge multiplicity for each endpoint equal to the node, plus the number
+ * of reads that begin with the node and the number that end with it.
+ *   DBG_NODES_KMERS      enumerate every k-mer of every read and sort them;
+ *   DBG_NODES_ENDPOINTS  sort 2 records per distinct edge (endpoint, weight =
+ *                        multiplicity) and 2 per read (its end k-mers, weight
+ *                        1), sum the weights and halve them;
+ *   DBG_NODES_AUTO       endpoints when their records number at most
+ *                        `endpoint_ratio` times the k-mers.
+ * Both give identical tables.  The endpoint route is taken only by single-set
+ * builds whose edge table fitted its capacity, that had at least one edge, and
+ * whose records fit the workspace's key buffers (records <= 8/12 of max_keys
+ * for k <= 31, 16/20 for k >= 33); otherwise the k-mers are enumerated. */
+typedef enum {
+  DBG_NODES_AUTO = -1,
+  DBG_NODES_KMERS = 0,
+  DBG_NODES_ENDPOINTS = 1
+} dbg_node_path;
+
+typedef struct {
+  int node_path;        /* dbg_node_path; default DBG_NODES_AUTO */
+  float endpoint_ratio; /* for DBG_NODES_AUTO; default 0.6 */
+  int reserved[6];      /* zero */
+} dbg_tuning_t;
+
+/* Process-wide tuning read by every later build call (calls in flight keep the
+ * values they started with).  NULL restores the defaults.  Returns DBG_E_ARG
+ * for an unknown node_path or a ratio outside [0, 2]. */
+int dbg_set_tuning(const dbg_tuning_t *tuning);
+/* Copies the current tuning into *tuning (DBG_E_NULL if null). */
+int dbg_get_tuning(dbg_tuning_t *tuning);
 
 /* Static description of a status code. */
 const char *dbg_strerror(int status);

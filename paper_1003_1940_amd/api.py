@@ -40,6 +40,13 @@ class _Edges(ctypes.Structure):
                 ("capacity", ctypes.c_uint64)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("node_path", ctypes.c_int), ("endpoint_ratio", ctypes.c_float),
+                ("reserved", ctypes.c_int * 6)]
+
+
+NODES_AUTO, NODES_KMERS, NODES_ENDPOINTS = -1, 0, 1
+
 _lib = None
 
 
@@ -62,10 +69,43 @@ def load():
                                           vp, vp, sz, vp]
         lib.dbg_pack_ascii.restype = i32
         lib.dbg_pack_ascii.argtypes = [vp, u64, vp, vp, vp]
+        lib.dbg_set_tuning.restype = i32
+        lib.dbg_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
+        lib.dbg_get_tuning.restype = i32
+        lib.dbg_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         lib.dbg_strerror.restype = ctypes.c_char_p
         lib.dbg_strerror.argtypes = [i32]
         _lib = lib
     return _lib
+
+
+def get_tuning() -> dict:
+    """The process-wide build tuning: node_path (NODES_AUTO, NODES_KMERS or
+    NODES_ENDPOINTS) and endpoint_ratio."""
+    t = _Tuning()
+    rc = load().dbg_get_tuning(ctypes.byref(t))
+    if rc:
+        raise DbgError(rc, "dbg_get_tuning")
+    return {"node_path": t.node_path, "endpoint_ratio": float(t.endpoint_ratio)}
+
+
+def set_tuning(node_path: int | None = None, endpoint_ratio: float | None = None,
+               defaults: bool = False) -> dict:
+    """Change the process-wide tuning (unnamed fields keep their values;
+    ``defaults=True`` first restores the library defaults).  Returns the new
+    tuning."""
+    lib = load()
+    if defaults:
+        rc = lib.dbg_set_tuning(None)
+        if rc:
+            raise DbgError(rc, "dbg_set_tuning")
+    cur = get_tuning()
+    t = _Tuning(cur["node_path"] if node_path is None else int(node_path),
+                cur["endpoint_ratio"] if endpoint_ratio is None else float(endpoint_ratio))
+    rc = lib.dbg_set_tuning(ctypes.byref(t))
+    if rc:
+        raise DbgError(rc, "dbg_set_tuning")
+    return get_tuning()
 
 
 def strerror(code: int) -> str:
@@ -220,6 +260,15 @@ def read_result(result) -> tuple:
     return int(r[0]), int(r[1]), int(r[2] & 0xFFFFFFFF)
 
 
+FLAG_NODES_FROM_ENDPOINTS = 1
+
+
+def read_flags(result) -> int:
+    """DBG_FLAG_* bits of a device result record (synchronises)."""
+    r = result.cpu().numpy().view(np.uint64)
+    return int(r[2] >> np.uint64(32))
+
+
 def upload(bases: np.ndarray, offsets: np.ndarray, device="cuda", stream=None):
     """ASCII reads (host) -> (packed words, device offsets, n_bases); packing runs
     on the device."""
@@ -238,24 +287,28 @@ def upload(bases: np.ndarray, offsets: np.ndarray, device="cuda", stream=None):
 
 
 def build(bases: np.ndarray, offsets: np.ndarray, k: int, zkey: bool = True, device="cuda",
-          node_cap: int | None = None, edge_cap: int | None = None) -> Graph:
+          node_cap: int | None = None, edge_cap: int | None = None,
+          max_keys: int | None = None) -> Graph:
     """Convenience: upload host reads, build, synchronise, return the device graph
-    sliced to its true sizes."""
+    sliced to its true sizes.  ``max_keys`` (at least the number of k-mer
+    positions, the default) sizes the workspace."""
     offsets = np.asarray(offsets, np.uint64)
     lens = np.diff(offsets.astype(np.int64))
     n_k = int(np.maximum(lens - k + 1, 0).sum()) if len(lens) else 0
+    max_keys = n_k if max_keys is None else max(int(max_keys), n_k)
     packed, offs, n_bases = upload(bases, offsets, device)
     node_cap = n_k if node_cap is None else node_cap
     edge_cap = n_k if edge_cap is None else edge_cap
     out = alloc_outputs(k, node_cap, edge_cap, device, zkey)
-    ws = Workspace(len(offsets) - 1, 1, n_k, k, device)
+    ws = Workspace(len(offsets) - 1, 1, max_keys, k, device)
     result = torch.zeros(3, dtype=torch.int64, device=device)
-    build_async(packed, n_bases, offs, k, n_k, out, node_cap, edge_cap, result, ws)
+    build_async(packed, n_bases, offs, k, max_keys, out, node_cap, edge_cap, result, ws)
     n_nodes, n_edges, status = read_result(result)
     if status not in (DBG_OK, DBG_E_CAPACITY):
         raise DbgError(status, "dbg_build (device)")
     g = Graph(k, out["node_kmer"], out["node_count"], out["edge_u"], out["edge_v"],
               out["edge_orient"], out["edge_mult"], out["edge_zkey"], n_nodes, n_edges, status)
+    g.extra["flags"] = read_flags(result)
     return g
 
 

@@ -1,15 +1,26 @@
 // C ABI of the graph builder: argument checks, workspace layout and dispatch on
 // the key width (64-bit keys for k <= 31, 128-bit keys for 33 <= k <= 63).
+#include <mutex>
+
 #include "dbg_internal.h"
 
 namespace dbg {
+
+// Process-wide tuning: copied under the lock at the start of each build call.
+static std::mutex g_tuning_mu;
+static dbg_tuning_t g_tuning = {DBG_NODES_AUTO, 0.6f, {0, 0, 0, 0, 0, 0}};
+
+static dbg_tuning_t current_tuning() {
+  std::lock_guard<std::mutex> lock(g_tuning_mu);
+  return g_tuning;
+}
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) {
   Layout L{};
   L.key_bytes = k <= 31 ? 8 : 16;
-  const uint64_t cap = k <= 31 ? local_cap<uint64_t>() : local_cap<unsigned __int128>();
+  const uint64_t cap = k <= 31 ? local_cap<uint64_t, true>() : local_cap<unsigned __int128, true>();
   const int edge_bits = 2 * (k + 1);
   const uint64_t levels = (uint64_t)((edge_bits + 7) / 8);  // digit levels incl. level 0
   L.max_tiles = (max_keys + TILE - 1) / TILE + n_sets;
@@ -45,7 +56,10 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) 
   L.bits = take(L.rle_tiles * (TILE / 8));
   L.set_uoff = 0;
   // key buffers: after the bucket sort buffer 0 holds distinct keys, buffer 1 their counts
-  for (int i = 0; i < 2; ++i) L.keys[i] = take((max_keys + 2) * (size_t)L.key_bytes);
+  const size_t kb = (max_keys + 2) * (size_t)L.key_bytes;
+  for (int i = 0; i < 2; ++i) L.keys[i] = take(kb);
+  // weighted records: keys in [0, R w), weights from here on (R <= this / w)
+  L.weights = (kb / (size_t)(L.key_bytes + 4) * (size_t)L.key_bytes) & ~size_t(15);
   L.total = off;
   return L;
 }
@@ -101,6 +115,7 @@ int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_off
   a.result = result;
   a.workspace = workspace;
   a.stream = stream;
+  a.tuning = dbg::current_tuning();
   return dbg::run(a, workspace_bytes);
 }
 
@@ -131,6 +146,7 @@ int dbg_build_batched(const uint64_t *packed, uint64_t n_bases, const uint64_t *
   a.result = result;
   a.workspace = workspace;
   a.stream = stream;
+  a.tuning = dbg::current_tuning();
   return dbg::run(a, workspace_bytes);
 }
 
@@ -145,6 +161,25 @@ int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
 int dbg_set_stage_events(hipEvent_t *events, int n_events) {
   if (events && n_events < DBG_STAGE_EVENTS) return DBG_E_ARG;
   dbg::set_stage_events(events);
+  return DBG_OK;
+}
+
+int dbg_set_tuning(const dbg_tuning_t *tuning) {
+  dbg_tuning_t t = {DBG_NODES_AUTO, 0.6f, {0, 0, 0, 0, 0, 0}};
+  if (tuning) {
+    if (tuning->node_path < DBG_NODES_AUTO || tuning->node_path > DBG_NODES_ENDPOINTS)
+      return DBG_E_ARG;
+    if (!(tuning->endpoint_ratio >= 0.0f && tuning->endpoint_ratio <= 2.0f)) return DBG_E_ARG;
+    t = *tuning;
+  }
+  std::lock_guard<std::mutex> lock(dbg::g_tuning_mu);
+  dbg::g_tuning = t;
+  return DBG_OK;
+}
+
+int dbg_get_tuning(dbg_tuning_t *tuning) {
+  if (!tuning) return DBG_E_NULL;
+  *tuning = dbg::current_tuning();
   return DBG_OK;
 }
 

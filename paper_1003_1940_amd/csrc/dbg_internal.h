@@ -19,20 +19,37 @@ constexpr uint64_t TILE = (uint64_t)STREAM_NT * STREAM_KPT;
 // consecutive small buckets of up to CAP keys entirely in LDS (see
 // k_local_sort): duplicates are merged in an LDS hash table of SLOTS slots, the
 // distinct keys are sorted, and the runs are expanded again.
-template <typename K> struct LocalCfg;
-template <> struct LocalCfg<uint64_t> {
+// W = true: weighted records (the node table built from edge endpoints), whose
+// 32-bit weights are summed instead of counted; their wider counts take LDS, so
+// the 64-bit variant holds fewer keys.
+template <typename K, bool W = false> struct LocalCfg;
+template <> struct LocalCfg<uint64_t, false> {
   static constexpr int NT = 512;
   static constexpr int CAP = 6144;
   static constexpr int SLOTS = 9216;
   static constexpr int SMALL = 16;  // segments sorted by one lane's network
 };
-template <> struct LocalCfg<unsigned __int128> {
+template <> struct LocalCfg<uint64_t, true> {
+  static constexpr int NT = 512;
+  static constexpr int CAP = 5120;
+  static constexpr int SLOTS = 7680;
+  static constexpr int SMALL = 16;
+};
+template <> struct LocalCfg<unsigned __int128, false> {
   static constexpr int NT = 512;
   static constexpr int CAP = 3072;
   static constexpr int SLOTS = 4608;
   static constexpr int SMALL = 8;
 };
-template <typename K> constexpr uint64_t local_cap() { return (uint64_t)LocalCfg<K>::CAP; }
+template <> struct LocalCfg<unsigned __int128, true> {
+  static constexpr int NT = 512;
+  static constexpr int CAP = 3072;
+  static constexpr int SLOTS = 4608;
+  static constexpr int SMALL = 8;
+};
+template <typename K, bool W = false> constexpr uint64_t local_cap() {
+  return (uint64_t)LocalCfg<K, W>::CAP;
+}
 
 // Most-significant-digit levels: level 0 is the enumeration scatter; a key of b
 // bits has ceil(b / 8) digits.
@@ -50,7 +67,8 @@ struct Ctl {
   uint64_t n_unique;        // distinct keys of the table
   uint64_t n_edges, n_nodes;
   uint32_t capacity_short;  // an output table had more rows than its capacity
-  uint32_t pad1;
+  uint32_t node_path;       // 0: node table from k-mers, 1: from edge endpoints
+  uint64_t n_records;       // weighted endpoint records (node_path 1)
 };
 
 struct Item {  // an oversized bucket: keys [off, off + size) of buffer `src`
@@ -68,6 +86,7 @@ struct Layout {
   size_t ctl, set_read_off, rbase, block_sums, set_kbase, set_tbase, tile_read, tile_set;
   size_t thist, csum, cursor0, items[2], hist[2], cursor, batches, uniform, rle_heads, bits, set_uoff;
   size_t keys[2];
+  size_t weights;  // byte offset of the record weights inside each key buffer
   size_t total;
   uint64_t max_tiles, item_cap, batch_cap, rle_tiles, read_blocks;
   int key_bytes;
@@ -91,6 +110,7 @@ struct BuildArgs {
   dbg_result_t *result;
   void *workspace;
   hipStream_t stream;
+  dbg_tuning_t tuning;
 };
 
 hipError_t run_build_u64(const BuildArgs &a, const Layout &L);

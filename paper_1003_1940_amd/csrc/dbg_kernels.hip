@@ -15,6 +15,8 @@
 //      STEP-3 dedup with counts), which also decodes edge records.
 // Keys carry no payload, so the partition passes need no stability: equal keys
 // are indistinguishable and every bucket is fully sorted in step 4.
+#include <type_traits>
+
 #include "dbg_device.h"
 #include "dbg_internal.h"
 
@@ -25,6 +27,13 @@ namespace dbg {
 
 __device__ __forceinline__ void set_status(Ctl *ctl, uint32_t code) {
   atomicCAS(&ctl->status, 0u, code);
+}
+
+// The node table has two routes (k-mers, or edge endpoints) chosen on the device;
+// a kernel of one route returns at once when the build took the other.  Gate -1:
+// the kernel belongs to both routes (and to the edge table).
+__device__ __forceinline__ bool gated_off(const Ctl *ctl, int gate) {
+  return gate >= 0 && (int)ctl->node_path != gate;
 }
 
 // First index i in [lo, hi) with a[i] > x (a ascending), hi if none.
@@ -229,6 +238,7 @@ struct EnumArgs {
   const uint32_t *tile_set;
   int len;   // bases per key
   int bits;  // 2 * len
+  int gate;
 };
 
 struct TileRange {
@@ -376,7 +386,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint32_t *t
   __shared__ uint32_t h[256];
   __shared__ EnumLds L;
   const uint64_t t = blockIdx.x;
-  if (ctl->status || t >= ctl->n_tiles) return;
+  if (ctl->status || gated_off(ctl, a.gate) || t >= ctl->n_tiles) return;
   h[threadIdx.x] = 0;
   const TileRange tr = enum_tile(a, t);
   const TileSrc ts = stage_tile(a, tr, L);
@@ -398,8 +408,8 @@ constexpr uint64_t COL_CHUNK = 128;
 constexpr int COL_BATCH = 16;  // independent loads in flight per thread
 
 __global__ __launch_bounds__(256) void k_col_reduce(const uint32_t *thist, uint32_t *csum,
-                                                    const Ctl *ctl) {
-  if (ctl->status) return;
+                                                    const Ctl *ctl, int gate) {
+  if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t nt = ctl->n_tiles;
   const uint64_t t0 = blockIdx.x * COL_CHUNK;
   if (t0 >= nt) return;
@@ -416,9 +426,9 @@ __global__ __launch_bounds__(256) void k_col_reduce(const uint32_t *thist, uint3
 }
 
 // One workgroup of 1024 threads: column d = tid % 256 is scanned in four parts.
-__global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const Ctl *ctl) {
+__global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const Ctl *ctl, int gate) {
   __shared__ uint32_t part[4][256];
-  if (ctl->status) return;
+  if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t nc = (ctl->n_tiles + COL_CHUNK - 1) / COL_CHUNK;
   const uint32_t d = threadIdx.x & 255, pi = threadIdx.x >> 8;
   const uint64_t q = (nc + 3) / 4;
@@ -449,8 +459,8 @@ __global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const Ctl *ct
 }
 
 __global__ __launch_bounds__(256) void k_col_apply(uint32_t *thist, const uint32_t *csum,
-                                                   const Ctl *ctl) {
-  if (ctl->status) return;
+                                                   const Ctl *ctl, int gate) {
+  if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t nt = ctl->n_tiles;
   const uint64_t t0 = blockIdx.x * COL_CHUNK;
   if (t0 >= nt && !(t0 == 0 && nt == 0)) return;
@@ -476,18 +486,20 @@ __global__ __launch_bounds__(256) void k_col_apply(uint32_t *thist, const uint32
 // digit-contiguously in LDS, then write each digit run with consecutive threads
 // on consecutive addresses.  `cursor` points at the 256 bucket cursors of the
 // parent.  Every thread of the workgroup must call it.
-template <typename K>
+template <typename K, bool W = false>
 struct PartLds {
   K keys[TILE];
+  uint32_t wts[W ? TILE : 1];  // record weights (W), moved with their keys
   uint64_t gbase[256];
   uint32_t cnt[256];
   uint64_t wsum[STREAM_NT / 64 + 1];
 };
 
-template <typename K>
-__device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT], int n, int bits,
+template <typename K, bool W = false>
+__device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
+                                               const uint32_t (&wts)[STREAM_KPT], int n, int bits,
                                                int level, uint64_t *cursor, uint64_t my_base,
-                                               K *dst, PartLds<K> &s) {
+                                               K *dst, uint32_t *dstw, PartLds<K, W> &s) {
   // cursor != null: reserve each digit's range with one atomic on cursor[d];
   // otherwise thread d already holds its digit's destination start in my_base.
   const uint32_t tid = threadIdx.x;
@@ -513,11 +525,17 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT], int 
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r)
-    if (r < n) s.keys[atomicAdd(&s.cnt[dig[r]], 1u)] = keys[r];
+    if (r < n) {
+      const uint32_t q = atomicAdd(&s.cnt[dig[r]], 1u);
+      s.keys[q] = keys[r];
+      if (W) s.wts[q] = wts[r];
+    }
   __syncthreads();
   for (uint32_t idx = tid; idx < (uint32_t)m; idx += STREAM_NT) {
     const K key = s.keys[idx];
-    dst[s.gbase[msd_digit(key, bits, level)] + idx] = key;
+    const uint64_t o = s.gbase[msd_digit(key, bits, level)] + idx;
+    dst[o] = key;
+    if (W) dstw[o] = s.wts[idx];
   }
   __syncthreads();
 }
@@ -531,7 +549,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
   __shared__ PartLds<K> s;
   __shared__ EnumLds L;
   const uint64_t t = blockIdx.x;
-  if (ctl->status || t >= ctl->n_tiles) return;
+  if (ctl->status || gated_off(ctl, a.gate) || t >= ctl->n_tiles) return;
   const TileRange tr = enum_tile(a, t);
   const TileSrc ts = stage_tile(a, tr, L);
   K keys[STREAM_KPT];
@@ -543,7 +561,8 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
   // holds fewer than 2^32 keys
   const uint64_t base = cursor0[(uint64_t)tr.set * 256 + d] +
                         (uint32_t)(tpre[t * 256 + d] - tpre[t_first * 256 + d]);
-  partition_tile<K>(keys, n, a.bits, 0, nullptr, base, dst, s);
+  const uint32_t nowt[STREAM_KPT] = {};
+  partition_tile<K>(keys, nowt, n, a.bits, 0, nullptr, base, dst, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -568,6 +587,7 @@ struct PlanArgs {
   Ctl *ctl;
   uint64_t local_cap;
   int bits;
+  int gate;
 };
 
 struct PlanLds {
@@ -651,7 +671,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_set_plan(PlanArgs p, const uint32
                                                         const uint64_t *set_kbase,
                                                         uint64_t n_sets) {
   __shared__ PlanLds lds;
-  if (p.ctl->status) return;
+  if (p.ctl->status || gated_off(p.ctl, p.gate)) return;
   const uint32_t d = threadIdx.x;
   for (uint64_t s = blockIdx.x; s < n_sets; s += gridDim.x) {
     const uint64_t c = (uint32_t)(tpre[set_tbase[s + 1] * 256 + d] - tpre[set_tbase[s] * 256 + d]);
@@ -665,9 +685,9 @@ __global__ __launch_bounds__(STREAM_NT) void k_set_plan(PlanArgs p, const uint32
 // One workgroup: tile offsets of the items of a list.
 __global__ __launch_bounds__(1024) void k_level_prep(Item *items, const uint64_t *n_items_p,
                                                      uint64_t *n_tiles_out, uint64_t *other_count,
-                                                     const Ctl *ctl) {
+                                                     const Ctl *ctl, int gate) {
   __shared__ uint64_t wsum[1024 / 64 + 1];
-  if (ctl->status) return;
+  if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t n = *n_items_p;
   uint64_t carry = 0;
   for (uint64_t c0 = 0; c0 < n; c0 += 1024) {
@@ -690,8 +710,10 @@ struct LevelArgs {
   const uint64_t *n_tiles_p;
   uint64_t *hist;
   uint64_t *cursor;
+  uint32_t *w0, *w1;  // record weights beside buffers 0 and 1 (weighted scatter)
   int bits;
   int level;
+  int gate;
 };
 
 __device__ __forceinline__ uint64_t find_item(const Item *items, uint64_t n, uint64_t t) {
@@ -723,7 +745,7 @@ template <typename K>
 __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K *b1,
                                                           const Ctl *ctl) {
   __shared__ uint32_t h[256];
-  if (ctl->status) return;
+  if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t n_tiles = *a.n_tiles_p, n_items = *a.n_items_p;
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint64_t ii = find_item(a.items, n_items, t);
@@ -747,7 +769,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K 
 
 __global__ __launch_bounds__(STREAM_NT) void k_level_plan(PlanArgs p, LevelArgs a) {
   __shared__ PlanLds lds;
-  if (p.ctl->status) return;
+  if (p.ctl->status || gated_off(p.ctl, p.gate)) return;
   const uint64_t n_items = *a.n_items_p;
   for (uint64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
     const Item it = a.items[ii];
@@ -756,11 +778,11 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_plan(PlanArgs p, LevelArgs 
   }
 }
 
-template <typename K>
+template <typename K, bool W>
 __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0, K *b1,
                                                              const Ctl *ctl) {
-  __shared__ PartLds<K> s;
-  if (ctl->status) return;
+  __shared__ PartLds<K, W> s;
+  if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t n_tiles = *a.n_tiles_p, n_items = *a.n_items_p;
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint64_t ii = find_item(a.items, n_items, t);
@@ -771,7 +793,10 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0,
     // keys are placed through LDS, so any assignment of keys to threads works:
     // use the coalesced strided one (valid keys form a prefix of each thread's)
     const int n = load_tile<K>(it.src ? b1 : b0, start, end, keys);
-    partition_tile<K>(keys, n, a.bits, a.level, a.cursor + ii * 256, 0, it.src ? b0 : b1, s);
+    uint32_t wts[STREAM_KPT] = {};
+    if (W) load_tile<uint32_t>(it.src ? a.w1 : a.w0, start, end, wts);
+    partition_tile<K, W>(keys, wts, n, a.bits, a.level, a.cursor + ii * 256, 0, it.src ? b0 : b1,
+                         it.src ? a.w0 : a.w1, s);
   }
 }
 
@@ -887,20 +912,24 @@ __device__ __forceinline__ uint64_t key_hash(u128 k) {
 // LDS of the bucket sort.  Buffer 0 (key0/cnt0) is where every finished piece
 // of the sorted distinct keys lands; the table region is reused for buffer 1
 // and, at the end, for the expanded keys.
-template <typename K>
+// Counts of distinct keys: 16 bits suffice for unweighted batches (at most CAP
+// keys); summed record weights (W) take 32.
+template <typename K, bool W>
 struct LocalLds {
-  static constexpr int NT = LocalCfg<K>::NT, NW = NT / 64, CAP = LocalCfg<K>::CAP;
-  static constexpr int SLOTS = LocalCfg<K>::SLOTS;
+  using Cfg = LocalCfg<K, W>;
+  using CT = typename std::conditional<W, uint32_t, uint16_t>::type;
+  static constexpr int NT = Cfg::NT, NW = NT / 64, CAP = Cfg::CAP;
+  static constexpr int SLOTS = Cfg::SLOTS;
   static constexpr size_t TBYTES_A = (size_t)SLOTS * 8;
-  static constexpr size_t TBYTES_B = (size_t)CAP * (sizeof(K) + 2);
+  static constexpr size_t TBYTES_B = (size_t)CAP * (sizeof(K) + sizeof(CT));
   static constexpr size_t TBYTES = TBYTES_A > TBYTES_B ? TBYTES_A : TBYTES_B;
   K key0[CAP];        // staged keys, then distinct keys (sorted in place)
-  uint16_t cnt0[CAP];
+  CT cnt0[CAP];
   uint16_t ulist[CAP];  // table slot of each distinct key, in discovery order
   alignas(16) unsigned char t[TBYTES];  // hash table | buffer 1
   uint32_t hist[NW][256];
   uint64_t large[2][CAP / 64 + 1];
-  uint64_t mid[CAP / (LocalCfg<K>::SMALL + 1) + 1];
+  uint64_t mid[CAP / (Cfg::SMALL + 1) + 1];
   uint32_t nlarge[2], nmid, nuniq, dirty;
   K wor[NW];
   K wand[NW];
@@ -908,20 +937,21 @@ struct LocalLds {
   __device__ uint32_t *own() { return reinterpret_cast<uint32_t *>(t); }
   __device__ uint32_t *tcnt() { return reinterpret_cast<uint32_t *>(t) + SLOTS; }
   __device__ K *key1() { return reinterpret_cast<K *>(t); }
-  __device__ uint16_t *cnt1() { return reinterpret_cast<uint16_t *>(t + (size_t)CAP * sizeof(K)); }
+  __device__ CT *cnt1() { return reinterpret_cast<CT *>(t + (size_t)CAP * sizeof(K)); }
   __device__ K *keys_of(uint32_t b) { return b ? key1() : key0; }
-  __device__ uint16_t *cnts_of(uint32_t b) { return b ? cnt1() : cnt0; }
+  __device__ CT *cnts_of(uint32_t b) { return b ? cnt1() : cnt0; }
 };
 
 // Finish or enqueue one segment [start, start+c) of distinct keys in buffer `buf`
 // whose keys agree above `shift`.  Called by one lane.
-template <typename K>
-__device__ __forceinline__ void classify_segment(LocalLds<K> &s, uint32_t start, uint32_t c,
+template <typename K, bool W>
+__device__ __forceinline__ void classify_segment(LocalLds<K, W> &s, uint32_t start, uint32_t c,
                                                  int shift, uint32_t buf, int nxt) {
-  constexpr int SMALL = LocalCfg<K>::SMALL;
+  using CT = typename LocalLds<K, W>::CT;
+  constexpr int SMALL = LocalCfg<K, W>::SMALL;
   if (c == 0) return;
   K *kb = s.keys_of(buf);
-  uint16_t *cb = s.cnts_of(buf);
+  CT *cb = s.cnts_of(buf);
   if (c == 1) {
     if (buf) {
       s.key0[start] = kb[start];
@@ -944,7 +974,7 @@ __device__ __forceinline__ void classify_segment(LocalLds<K> &s, uint32_t start,
     for (int j = 0; j < SMALL; ++j)
       if ((uint32_t)j < c) {
         s.key0[start + j] = v[j];
-        s.cnt0[start + j] = (uint16_t)w[j];
+        s.cnt0[start + j] = (CT)w[j];
       }
   } else if (c <= 64) {
     s.mid[atomicAdd(&s.nmid, 1u)] = seg_pack(start, c, shift, buf);
@@ -986,17 +1016,21 @@ __device__ __forceinline__ void mark_positions(uint32_t *bits, uint64_t off, uin
   }
 }
 
-template <typename K>
-__global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *batches,
-                                                                const uint64_t *n_batches_p,
-                                                                K *b0, K *b1, uint32_t *bits,
-                                                                const Ctl *ctl) {
-  using Cfg = LocalCfg<K>;
+// W: weighted records (node table from edge endpoints): the weights, stored
+// beside the keys in w0 / w1, are summed per distinct key instead of counting
+// occurrences, and the sum is halved on output (each k-mer occurrence is seen
+// twice).
+template <typename K, bool W>
+__global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
+    const Batch *batches, const uint64_t *n_batches_p, K *b0, K *b1, const uint32_t *w0,
+    const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate) {
+  using Cfg = LocalCfg<K, W>;
+  using CT = typename LocalLds<K, W>::CT;
   constexpr int NT = Cfg::NT, NW = NT / 64, SLOTS = Cfg::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
-  constexpr int LPT = (LocalCfg<K>::CAP + NT - 1) / NT;  // keys per thread
-  __shared__ LocalLds<K> s;
-  if (ctl->status) return;
+  constexpr int LPT = (Cfg::CAP + NT - 1) / NT;  // keys per thread
+  __shared__ LocalLds<K, W> s;
+  if (ctl->status || gated_off(ctl, gate)) return;
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const uint64_t n_batches = *n_batches_p;
   const uint64_t G = gridDim.x;
@@ -1004,12 +1038,21 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
   // software pipeline: the keys of the next batch are loaded into registers
   // while this one is processed in LDS (descriptors are read two batches ahead)
   K pre[LPT];
+  uint32_t prew[W ? LPT : 1], cw[W ? LPT : 1];
   auto prefetch = [&](const Batch &b) {
     const K *src = b.src ? b1 : b0;
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
       const uint32_t e = tid + (uint32_t)j * NT;
       pre[j] = e < b.size ? src[b.off + e] : K(0);
+    }
+    if (W) {
+      const uint32_t *srcw = b.src ? w1 : w0;
+#pragma unroll
+      for (int j = 0; j < LPT; ++j) {
+        const uint32_t e = tid + (uint32_t)j * NT;
+        prew[j] = e < b.size ? srcw[b.off + e] : 0u;
+      }
     }
   };
   if (tid == 0) s.dirty = 1;  // the table starts uninitialised
@@ -1031,6 +1074,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
         kor |= pre[j];
         kand &= pre[j];
       }
+      if (W) cw[j] = prew[j];  // this batch's weights stay with the thread that hashes them
     }
     kor = wave_or_key(kor);
     kand = wave_and_key(kand);
@@ -1084,7 +1128,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
             o = atomicCAS(&own[h], EMPTY, e);
           }
           claimed = o == EMPTY;
-          atomicAdd(&tcnt[h], 1u);
+          atomicAdd(&tcnt[h], W ? cw[j] : 1u);
         }
         // the lane that claimed a slot records it: one LDS atomic per wave
         const uint64_t cm = __ballot(claimed);
@@ -1108,7 +1152,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
     // 3. distinct keys (read from the table into registers through the list of
     //    claimed slots) partitioned by the 8 bits below hb straight into buffer 0
     const uint32_t nu = s.nuniq;
-    constexpr int UPT = (LocalCfg<K>::CAP + NT - 1) / NT;
+    constexpr int UPT = (Cfg::CAP + NT - 1) / NT;
     K uk[UPT];
     uint32_t uc[UPT], ud[UPT];
 #pragma unroll
@@ -1135,14 +1179,14 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < UPT; ++j)
-      if (uc[j]) {
+      if (tid + (uint32_t)j * NT < nu) {
         const uint32_t q = atomicAdd(&s.hist[0][ud[j]], 1u);
         s.key0[q] = uk[j];
-        s.cnt0[q] = (uint16_t)uc[j];
+        s.cnt0[q] = (CT)uc[j];
       }
     __syncthreads();
     int cur = 0;
-    if (tid < 256) classify_segment<K>(s, st, c, hb > 0 ? hb - 8 : 0, 0u, 0);
+    if (tid < 256) classify_segment<K, W>(s, st, c, hb > 0 ? hb - 8 : 0, 0u, 0);
     while (true) {
       __syncthreads();
       // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
@@ -1150,7 +1194,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
         const uint64_t d = s.mid[i];
         const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
         const K *kb = s.keys_of(buf);
-        const uint16_t *cb = s.cnts_of(buf);
+        const CT *cb = s.cnts_of(buf);
         {
           const uint32_t me = lane;
           const K x = me < c ? kb[st + me] : all_ones<K>();
@@ -1162,7 +1206,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
           // operations of one wave complete in order)
           if (me < c) {
             s.key0[st + rank] = x;
-            s.cnt0[st + rank] = (uint16_t)xc;
+            s.cnt0[st + rank] = (CT)xc;
           }
         }
       }
@@ -1177,9 +1221,9 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
         const uint64_t d = s.large[cur][i];
         const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
         const K *ik = s.keys_of(buf);
-        const uint16_t *ic = s.cnts_of(buf);
+        const CT *ic = s.cnts_of(buf);
         K *ok = s.keys_of(buf ^ 1u);
-        uint16_t *oc = s.cnts_of(buf ^ 1u);
+        CT *oc = s.cnts_of(buf ^ 1u);
         if (buf == 0 && lane == 0) s.dirty = 1;  // buffer 1 overwrites the hash table
         uint32_t *h = s.hist[w];
         K dd = 0;
@@ -1207,7 +1251,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          classify_segment<K>(s, base + pre[q], cnt[q], shift - 8, buf ^ 1u, cur ^ 1);
+          classify_segment<K, W>(s, base + pre[q], cnt[q], shift - 8, buf ^ 1u, cur ^ 1);
       }
       __syncthreads();
       if (tid == 0) s.nlarge[cur] = 0;
@@ -1219,7 +1263,7 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
     //    bitmap marks those positions
     for (uint32_t u = tid; u < nu; u += NT) {
       b0[bt.off + u] = s.key0[u];
-      b1[bt.off + u] = (K)(uint32_t)s.cnt0[u];
+      b1[bt.off + u] = (K)((uint32_t)s.cnt0[u] >> (W ? 1 : 0));
     }
     mark_positions(bits, bt.off, m, nu);
     __syncthreads();
@@ -1230,8 +1274,8 @@ __global__ __launch_bounds__(LocalCfg<K>::NT) void k_local_sort(const Batch *bat
 // distinct key whose count is the bucket size.
 template <typename K>
 __global__ void k_uniform_emit(const Item *uni, const uint64_t *n_uni_p, K *b0, K *b1,
-                               uint32_t *bits, const Ctl *ctl) {
-  if (ctl->status) return;
+                               uint32_t *bits, const Ctl *ctl, int gate) {
+  if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t n = *n_uni_p;
   for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < n;
        u += (uint64_t)gridDim.x * blockDim.x) {
@@ -1240,6 +1284,110 @@ __global__ void k_uniform_emit(const Item *uni, const uint64_t *n_uni_p, K *b0, 
     b0[it.off] = key;
     b1[it.off] = (K)it.size;
     atomicOr(&bits[it.off >> 5], 1u << (it.off & 31));
+  }
+}
+
+// Weighted records: the bucket's count is half the sum of its weights; one
+// workgroup per bucket.
+template <typename K>
+__global__ __launch_bounds__(256) void k_uniform_emit_w(const Item *uni, const uint64_t *n_uni_p,
+                                                        K *b0, K *b1, const uint32_t *w0,
+                                                        const uint32_t *w1, uint32_t *bits,
+                                                        const Ctl *ctl, int gate) {
+  __shared__ uint64_t wsum[256 / 64 + 1];
+  if (ctl->status || gated_off(ctl, gate)) return;
+  const uint64_t n = *n_uni_p;
+  for (uint64_t u = blockIdx.x; u < n; u += gridDim.x) {
+    const Item it = uni[u];
+    const uint32_t *wt = it.src ? w1 : w0;
+    uint64_t sum = 0;
+    for (uint64_t i = threadIdx.x; i < it.size; i += 256) sum += wt[it.off + i];
+    uint64_t tot;
+    block_exclusive_scan<256>(sum, wsum, &tot);
+    if (threadIdx.x == 0) {
+      const K key = (it.src ? b1 : b0)[it.off];
+      b0[it.off] = key;
+      b1[it.off] = (K)(tot >> 1);
+      atomicOr(&bits[it.off >> 5], 1u << (it.off & 31));
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node table from edge endpoints (STEP-3 of Sec. 3 with counts).  Each distinct
+// edge (u, v, multiplicity m) gives the records (u, m) and (v, m); each read of
+// at least k bases gives (canonical first k-mer, 1) and (canonical last k-mer,
+// 1).  Every k-mer occurrence is counted twice over these records, so a node's
+// count is half its summed weight.  Reads shorter than k give two records of
+// weight 0 on the first edge's u (an existing node), which leave every count
+// unchanged and keep the record index a plain function of the read index.
+
+// Chooses the route of the node table (after the node table's key offsets are
+// known and the edge table is complete).
+__global__ void k_node_path(Ctl *ctl, uint64_t n_reads, uint64_t n_sets, int mode, float ratio,
+                            uint64_t key_buf_bytes, uint64_t weight_off, int key_bytes) {
+  if (threadIdx.x || blockIdx.x) return;
+  ctl->node_path = 0;
+  ctl->n_records = 0;
+  if (ctl->status || mode == 0) return;
+  const uint64_t ne = ctl->n_edges, nk = ctl->n_keys;
+  const uint64_t r = 2 * ne + 2 * n_reads;
+  const bool fits = r * (uint64_t)key_bytes <= weight_off && weight_off + 4 * r <= key_buf_bytes;
+  const bool ok = n_sets == 1 && !ctl->capacity_short && ne > 0 && nk < (1ull << 31) && fits;
+  const bool take = ok && (mode == 1 || (double)r <= (double)ratio * (double)nk);
+  if (take) {
+    ctl->node_path = 1;
+    ctl->n_records = r;
+  }
+}
+
+template <typename K>
+__global__ void k_rec_edges(const K *u, const K *v, const uint32_t *mult, K *keys,
+                            uint32_t *wts, const Ctl *ctl) {
+  if (ctl->status || ctl->node_path != 1) return;
+  const uint64_t ne = ctl->n_edges;
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < ne;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t m = mult[j];
+    keys[2 * j] = u[j];
+    keys[2 * j + 1] = v[j];
+    wts[2 * j] = m;
+    wts[2 * j + 1] = m;
+  }
+}
+
+template <typename K>
+__global__ void k_rec_ends(const uint64_t *packed, uint64_t n_words, const uint64_t *offsets,
+                           uint64_t n_reads, int k, const K *u, K *keys, uint32_t *wts,
+                           const Ctl *ctl) {
+  if (ctl->status || ctl->node_path != 1) return;
+  const uint64_t base = 2 * ctl->n_edges;
+  const K filler = u[0];
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_reads;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t a = offsets[i], b = offsets[i + 1];
+    K first = filler, last = filler;
+    uint32_t w = 0;
+    if (b >= a && b - a >= (uint64_t)k) {
+      first = canonical<K>(extract_bases(packed, n_words, a, k, K(0)), k);
+      last = canonical<K>(extract_bases(packed, n_words, b - (uint64_t)k, k, K(0)), k);
+      w = 1;
+    }
+    keys[base + 2 * i] = first;
+    keys[base + 2 * i + 1] = last;
+    wts[base + 2 * i] = w;
+    wts[base + 2 * i + 1] = w;
+  }
+}
+
+// The records as one level-0 bucket of list 0.
+__global__ void k_rec_init(Ctl *ctl, Item *items0, uint64_t *hist0) {
+  if (ctl->status || ctl->node_path != 1) return;
+  hist0[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    items0[0] = Item{0, ctl->n_records, 0, 0u, 0u};
+    ctl->items[0] = 1;
   }
 }
 
@@ -1348,7 +1496,7 @@ __global__ void k_write_result(const Ctl *ctl, dbg_result_t *res) {
   res->n_nodes = ctl->n_nodes;
   res->n_edges = ctl->n_edges;
   res->status = ctl->status ? ctl->status : (ctl->capacity_short ? (uint32_t)DBG_E_CAPACITY : 0u);
-  res->reserved = 0;
+  res->flags = ctl->node_path == 1 ? DBG_FLAG_NODES_FROM_ENDPOINTS : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1433,11 +1581,19 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   K *x0 = reinterpret_cast<K *>(ws + L.keys[0]);
   K *x1 = reinterpret_cast<K *>(ws + L.keys[1]);
   uint32_t *runbits = reinterpret_cast<uint32_t *>(ws + L.bits);
+  uint32_t *wt0 = reinterpret_cast<uint32_t *>(ws + L.keys[0] + L.weights);
+  uint32_t *wt1 = reinterpret_cast<uint32_t *>(ws + L.keys[1] + L.weights);
   hipStream_t st = A.stream;
   const uint64_t S = A.n_sets;
   const int len = edges ? A.k + 1 : A.k;
   const int bits = 2 * len;
   const int ev = edges ? 0 : 10;
+  // The node table of a single-set build may be built from the edge endpoints
+  // instead of the k-mers; the device picks the route (k_node_path) and the
+  // kernels of the other route return at once.  g0 gates the k-mer route.
+  const bool two_routes = !edges && S == 1 && A.tuning.node_path != DBG_NODES_KMERS;
+  const int g0 = two_routes ? 0 : -1;
+  const uint64_t n_words = (A.n_bases + 31) / 32;
 
   stage(ev + 0, st);
   hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(1), 0, st, ctl);
@@ -1452,46 +1608,97 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   hipLaunchKernelGGL(k_tile_map, dim3(grid_for(L.max_tiles, 256, 1u << 30)), dim3(256), 0, st,
                      rbase, set_read_off, S, set_kbase, set_tbase, tile_read, tile_set,
                      L.max_tiles, ctl);
+  if (two_routes)
+    hipLaunchKernelGGL(k_node_path, dim3(1), dim3(1), 0, st, ctl, A.n_reads, S,
+                       A.tuning.node_path, A.tuning.endpoint_ratio,
+                       (uint64_t)(A.max_keys + 2) * (uint64_t)L.key_bytes, (uint64_t)L.weights,
+                       L.key_bytes);
   stage(ev + 1, st);
-  EnumArgs ea{A.packed, (A.n_bases + 31) / 32, A.read_offsets, rbase, set_read_off, set_kbase,
-              set_tbase, tile_read, tile_set, len, bits};
+  EnumArgs ea{A.packed, n_words, A.read_offsets, rbase, set_read_off, set_kbase,
+              set_tbase, tile_read, tile_set, len, bits, g0};
   hipLaunchKernelGGL(k_enum_hist<K>, dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st, ea,
                      thist, ctl);
+  if (two_routes) {
+    const K *eu = static_cast<const K *>(A.edges.u);
+    hipLaunchKernelGGL(k_rec_edges<K>, dim3(grid_for(A.edges.capacity, 256, 8192)), dim3(256), 0,
+                       st, eu, static_cast<const K *>(A.edges.v), A.edges.mult, x0, wt0, ctl);
+    hipLaunchKernelGGL(k_rec_ends<K>, dim3(grid_for(A.n_reads, 256, 8192)), dim3(256), 0, st,
+                       A.packed, n_words, A.read_offsets, A.n_reads, A.k, eu, x0, wt0, ctl);
+  }
   stage(ev + 2, st);
   const unsigned col_chunks = (unsigned)((L.max_tiles + COL_CHUNK - 1) / COL_CHUNK);
-  hipLaunchKernelGGL(k_col_reduce, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl);
-  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, ctl);
-  hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl);
+  hipLaunchKernelGGL(k_col_reduce, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl, g0);
+  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, ctl, g0);
+  hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl, g0);
   PlanArgs pa{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
-              uniform, L.item_cap, ctl, local_cap<K>(), bits};
+              uniform, L.item_cap, ctl, local_cap<K>(), bits, g0};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
+  const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 2048);
+  // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
+  LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], cursor, wt0, wt1,
+                bits, 0, 1};
+  if (two_routes) {
+    hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, st, ctl, items[0], hist[0]);
+    hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[0], &ctl->items[0],
+                       &ctl->level_tiles[0], &ctl->items[1], ctl, 1);
+    hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la0, x0, x1,
+                       ctl);
+    PlanArgs pw{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
+                uniform, L.item_cap, ctl, local_cap<K, true>(), bits, 1};
+    hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
+                       pw, la0);
+  }
   stage(ev + 3, st);
   hipLaunchKernelGGL(k_enum_scatter<K>, dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st, ea,
                      cursor0, thist, x0, ctl);
+  if (two_routes)
+    hipLaunchKernelGGL((k_level_scatter<K, true>), dim3(level_grid), dim3(STREAM_NT), 0, st, la0,
+                       x0, x1, ctl);
   stage(ev + 4, st);
-  const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 2048);
   for (int lev = 1; bits - 8 * lev > 0; ++lev) {
     const int li = lev & 1;
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[li], &ctl->items[li],
-                       &ctl->level_tiles[li], &ctl->items[li ^ 1], ctl);
-    LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li], hist[li], cursor, bits, lev};
+                       &ctl->level_tiles[li], &ctl->items[li ^ 1], ctl, -1);
+    LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li], hist[li], cursor, wt0, wt1,
+                 bits, lev, -1};
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
     PlanArgs pl{items[li ^ 1], &ctl->items[li ^ 1], hist[li ^ 1], L.item_cap, batches,
-                L.batch_cap, uniform, L.item_cap, ctl, local_cap<K>(), bits};
+                L.batch_cap, uniform, L.item_cap, ctl, local_cap<K>(), bits, g0};
     hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
                        pl, la);
-    hipLaunchKernelGGL(k_level_scatter<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1,
-                       ctl);
+    if (two_routes) {
+      PlanArgs pw = pl;
+      pw.local_cap = local_cap<K, true>();
+      pw.gate = 1;
+      hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0,
+                         st, pw, la);
+    }
+    la.gate = g0;
+    hipLaunchKernelGGL((k_level_scatter<K, false>), dim3(level_grid), dim3(STREAM_NT), 0, st, la,
+                       x0, x1, ctl);
+    if (two_routes) {
+      la.gate = 1;
+      hipLaunchKernelGGL((k_level_scatter<K, true>), dim3(level_grid), dim3(STREAM_NT), 0, st, la,
+                         x0, x1, ctl);
+    }
   }
   stage(ev + 5, st);
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.rle_tiles * (TILE / 64), 256, 8192)), dim3(256), 0,
                      st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
-  hipLaunchKernelGGL(k_local_sort<K>, dim3(grid_for(L.batch_cap, 1, 2048)), dim3(LocalCfg<K>::NT),
-                     0, st, batches, &ctl->n_batches, x0, x1, runbits, ctl);
+  hipLaunchKernelGGL((k_local_sort<K, false>), dim3(grid_for(L.batch_cap, 1, 2048)),
+                     dim3(LocalCfg<K>::NT), 0, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
+                     runbits, ctl, g0);
+  if (two_routes)
+    hipLaunchKernelGGL((k_local_sort<K, true>), dim3(grid_for(L.batch_cap, 1, 2048)),
+                       dim3(LocalCfg<K, true>::NT), 0, st, batches, &ctl->n_batches, x0, x1, wt0,
+                       wt1, runbits, ctl, 1);
   stage(ev + 6, st);
   hipLaunchKernelGGL(k_uniform_emit<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
-                     x1, runbits, ctl);
+                     x1, runbits, ctl, g0);
+  if (two_routes)
+    hipLaunchKernelGGL(k_uniform_emit_w<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform,
+                       x0, x1, wt0, wt1, runbits, ctl, 1);
   hipLaunchKernelGGL(k_emit_count, dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st, runbits,
                      rle_heads, ctl);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, rle_heads, L.rle_tiles,

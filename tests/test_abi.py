@@ -24,8 +24,9 @@ def lib():
 
 
 def test_header_declares_entry_points():
-    assert declared_functions() == ["dbg_build", "dbg_build_batched", "dbg_pack_ascii",
-                                    "dbg_set_stage_events", "dbg_strerror", "dbg_workspace_bytes"]
+    assert declared_functions() == ["dbg_build", "dbg_build_batched", "dbg_get_tuning",
+                                    "dbg_pack_ascii", "dbg_set_stage_events", "dbg_set_tuning",
+                                    "dbg_strerror", "dbg_workspace_bytes"]
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -75,3 +76,19 @@ def test_host_rejects_bad_arguments(lib):
     assert _call_build(lib, offsets_null=True) == 1
     assert _call_build(lib, max_keys=1 << 32) == 4  # DBG_E_OVERFLOW: counts are 32-bit
     assert _call_build(lib, ws_bytes=100) == 6      # DBG_E_WORKSPACE
+
+
+def test_tuning_round_trip(lib):
+    from paper_1003_1940_amd import api
+    d = api.set_tuning(defaults=True)
+    assert d == {"node_path": api.NODES_AUTO, "endpoint_ratio": pytest.approx(0.6)}
+    assert api.set_tuning(node_path=api.NODES_ENDPOINTS)["node_path"] == api.NODES_ENDPOINTS
+    assert api.set_tuning(endpoint_ratio=0.25)["endpoint_ratio"] == pytest.approx(0.25)
+    assert api.get_tuning()["node_path"] == api.NODES_ENDPOINTS  # unnamed field kept
+    for bad in (dict(node_path=2), dict(node_path=-2), dict(endpoint_ratio=-0.1),
+                dict(endpoint_ratio=3.0)):
+        with pytest.raises(api.DbgError):
+            api.set_tuning(**bad)
+    assert api.get_tuning()["endpoint_ratio"] == pytest.approx(0.25)  # refused: unchanged
+    assert lib.dbg_get_tuning(None) == 1
+    api.set_tuning(defaults=True)
