@@ -893,6 +893,27 @@ __device__ __forceinline__ void sort_network_kv(K (&v)[N], uint32_t (&c)[N]) {
           }
 }
 
+// One lane sorts c <= N (key, count) pairs of a segment into buffer 0.
+template <int N, typename K, typename CT>
+__device__ __forceinline__ void network_segment(const K *kb, const CT *cb, K *k0, CT *c0,
+                                                uint32_t start, uint32_t c) {
+  K v[N];
+  uint32_t w[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool in = (uint32_t)j < c;
+    v[j] = in ? kb[start + j] : all_ones<K>();
+    w[j] = in ? (uint32_t)cb[start + j] : 0u;
+  }
+  sort_network_kv<N, K>(v, w);
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+    if ((uint32_t)j < c) {
+      k0[start + j] = v[j];
+      c0[start + j] = (CT)w[j];
+    }
+}
+
 // segment descriptor: start, size (16 bits each), shift + 128 (8 bits), buffer (1 bit)
 __device__ __forceinline__ uint64_t seg_pack(uint32_t start, uint32_t size, int shift,
                                              uint32_t buf) {
@@ -960,22 +981,20 @@ __device__ __forceinline__ void classify_segment(LocalLds<K, W> &s, uint32_t sta
     return;
   }
   // distinct keys: c >= 2 always leaves bits to split on (shift > 0)
-  if (c <= (uint32_t)SMALL) {
-    K v[SMALL];
-    uint32_t w[SMALL];
-#pragma unroll
-    for (int j = 0; j < SMALL; ++j) {
-      const bool in = (uint32_t)j < c;
-      v[j] = in ? kb[start + j] : all_ones<K>();
-      w[j] = in ? cb[start + j] : 0u;
-    }
-    sort_network_kv<SMALL, K>(v, w);
-#pragma unroll
-    for (int j = 0; j < SMALL; ++j)
-      if ((uint32_t)j < c) {
-        s.key0[start + j] = v[j];
-        s.cnt0[start + j] = (CT)w[j];
-      }
+  if (c == 2) {
+    const K x = kb[start], y = kb[start + 1];
+    const CT cx = cb[start], cy = cb[start + 1];
+    const bool sw = y < x;
+    s.key0[start] = sw ? y : x;
+    s.key0[start + 1] = sw ? x : y;
+    s.cnt0[start] = sw ? cy : cx;
+    s.cnt0[start + 1] = sw ? cx : cy;
+  } else if (c <= 4) {
+    network_segment<4, K, CT>(kb, cb, s.key0, s.cnt0, start, c);
+  } else if (c <= 8) {
+    network_segment<8, K, CT>(kb, cb, s.key0, s.cnt0, start, c);
+  } else if (c <= (uint32_t)SMALL) {
+    network_segment<SMALL, K, CT>(kb, cb, s.key0, s.cnt0, start, c);
   } else if (c <= 64) {
     s.mid[atomicAdd(&s.nmid, 1u)] = seg_pack(start, c, shift, buf);
   } else {
@@ -1029,6 +1048,7 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
   constexpr int NT = Cfg::NT, NW = NT / 64, SLOTS = Cfg::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
   constexpr int LPT = (Cfg::CAP + NT - 1) / NT;  // keys per thread
+  static_assert(4 * NT >= 2048, "the first partition uses up to 2048 bins, 4 per thread");
   __shared__ LocalLds<K, W> s;
   if (ctl->status || gated_off(ctl, gate)) return;
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
@@ -1038,7 +1058,7 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
   // software pipeline: the keys of the next batch are loaded into registers
   // while this one is processed in LDS (descriptors are read two batches ahead)
   K pre[LPT];
-  uint32_t prew[W ? LPT : 1], cw[W ? LPT : 1];
+  uint32_t prew[W ? LPT : 1];
   auto prefetch = [&](const Batch &b) {
     const K *src = b.src ? b1 : b0;
 #pragma unroll
@@ -1074,7 +1094,6 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
         kor |= pre[j];
         kand &= pre[j];
       }
-      if (W) cw[j] = prew[j];  // this batch's weights stay with the thread that hashes them
     }
     kor = wave_or_key(kor);
     kand = wave_and_key(kand);
@@ -1082,9 +1101,6 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
       s.wor[w] = kor;
       s.wand[w] = kand;
     }
-    nxt = nxt2;
-    nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
-    if (bi + G < n_batches) prefetch(nxt);
     if (s.dirty) {  // uniform: read after the previous batch's final barrier
       for (uint32_t q = tid; q < (uint32_t)SLOTS; q += NT) {
         own[q] = EMPTY;
@@ -1098,7 +1114,7 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
       s.nuniq = 0;
       s.dirty = 0;
     }
-    if (tid < 256) s.hist[0][tid] = 0;
+    for (uint32_t q = tid; q < (uint32_t)(NW * 256); q += NT) s.hist[0][q] = 0;
     __syncthreads();
     // 2. count duplicates in an LDS hash table keyed by the first occurrence
     {
@@ -1111,7 +1127,7 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
         hs[j] = 0;
         os[j] = EMPTY;
         if (e < m) {
-          hs[j] = (uint32_t)(((key_hash(s.key0[e]) >> 32) * (uint64_t)SLOTS) >> 32);
+          hs[j] = (uint32_t)(((key_hash(pre[j]) >> 32) * (uint64_t)SLOTS) >> 32);
           os[j] = atomicCAS(&own[hs[j]], EMPTY, e);
         }
       }
@@ -1121,14 +1137,14 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
         bool claimed = false;
         uint32_t h = hs[j];
         if (e < m) {
-          const K key = s.key0[e];
+          const K key = pre[j];
           uint32_t o = os[j];
           while (o != EMPTY && s.key0[o] != key) {
             h = h + 1 == (uint32_t)SLOTS ? 0u : h + 1;
             o = atomicCAS(&own[h], EMPTY, e);
           }
           claimed = o == EMPTY;
-          atomicAdd(&tcnt[h], W ? cw[j] : 1u);
+          atomicAdd(&tcnt[h], W ? prew[j] : 1u);
         }
         // the lane that claimed a slot records it: one LDS atomic per wave
         const uint64_t cm = __ballot(claimed);
@@ -1142,6 +1158,11 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
       }
     }
     __syncthreads();
+    // the next batch's keys load while this one is sorted (descriptors are read
+    // two batches ahead)
+    nxt = nxt2;
+    nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
+    if (bi + G < n_batches) prefetch(nxt);
     K kall_or = 0, kall_and = all_ones<K>();
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
@@ -1152,6 +1173,13 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
     // 3. distinct keys (read from the table into registers through the list of
     //    claimed slots) partitioned by the 8 bits below hb straight into buffer 0
     const uint32_t nu = s.nuniq;
+    // digit width: about one distinct key per bucket, 8 to 11 bits, taken just
+    // below hb
+    int dw = nu <= 256 ? 8 : bit_length((uint64_t)(nu - 1));
+    dw = dw > 11 ? 11 : dw;
+    dw = dw > hb ? hb : dw;
+    const int dshift = hb - dw;
+    uint32_t *H = &s.hist[0][0];  // NW * 256 = 2048 bins
     constexpr int UPT = (Cfg::CAP + NT - 1) / NT;
     K uk[UPT];
     uint32_t uc[UPT], ud[UPT];
@@ -1165,28 +1193,67 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
         const uint32_t q = s.ulist[u];
         uk[j] = s.key0[own[q]];
         uc[j] = tcnt[q];
-        ud[j] = hb > 0 ? seg_digit(uk[j], hb) : 0u;
-        atomicAdd(&s.hist[0][ud[j]], 1u);
+        ud[j] = dw > 0 ? (uint32_t)shr<K>(uk[j], dshift) & ((1u << dw) - 1u) : 0u;
+        atomicAdd(&H[ud[j]], 1u);
         own[q] = EMPTY;  // leave the table clean for the next batch
         tcnt[q] = 0;
       }
     }
     __syncthreads();
-    const uint32_t c = tid < 256 ? s.hist[0][tid] : 0u;
+    // thread t owns bins 4t .. 4t+3
+    uint32_t c4[4], st4[4], sum4 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c4[q] = H[4 * tid + q];
+      sum4 += c4[q];
+    }
     uint32_t tot;
-    const uint32_t st = block_exclusive_scan<NT>(c, s.wsum, &tot);
-    if (tid < 256) s.hist[0][tid] = st;
+    uint32_t run = block_exclusive_scan<NT>(sum4, s.wsum, &tot);
+    uint16_t *bstart = s.ulist;  // the list is read out: it now keeps the bucket starts
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      st4[q] = run;
+      H[4 * tid + q] = run;
+      bstart[4 * tid + q] = (uint16_t)run;
+      run += c4[q];
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < UPT; ++j)
       if (tid + (uint32_t)j * NT < nu) {
-        const uint32_t q = atomicAdd(&s.hist[0][ud[j]], 1u);
+        const uint32_t q = atomicAdd(&H[ud[j]], 1u);
         s.key0[q] = uk[j];
         s.cnt0[q] = (CT)uc[j];
       }
     __syncthreads();
+    // buckets of up to 64 keys: every distinct key counts the smaller keys of
+    // its bucket, then all of them move to their final places at once (the
+    // reads finish before the barrier, so the moves can be in place)
+    constexpr uint32_t NOPOS = 0xffffffffu;
+    uint32_t fin[UPT];
+#pragma unroll
+    for (int j = 0; j < UPT; ++j) {
+      fin[j] = NOPOS;
+      if (tid + (uint32_t)j * NT < nu) {
+        const uint32_t b = bstart[ud[j]], e = H[ud[j]];
+        if (e - b <= 64u) {
+          uint32_t r = 0;
+          for (uint32_t i = b; i < e; ++i) r += s.key0[i] < uk[j] ? 1u : 0u;
+          fin[j] = b + r;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < UPT; ++j)
+      if (fin[j] != NOPOS) {
+        s.key0[fin[j]] = uk[j];
+        s.cnt0[fin[j]] = (CT)uc[j];
+      }
     int cur = 0;
-    if (tid < 256) classify_segment<K, W>(s, st, c, hb > 0 ? hb - 8 : 0, 0u, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (c4[q] > 64u) classify_segment<K, W>(s, st4[q], c4[q], dshift, 0u, 0);
     while (true) {
       __syncthreads();
       // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
