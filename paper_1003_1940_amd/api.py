@@ -337,3 +337,55 @@ def build_batched(bases: np.ndarray, offsets: np.ndarray, set_read_offsets: np.n
     return Graph(k, out["node_kmer"], out["node_count"], out["edge_u"], out["edge_v"],
                  out["edge_orient"], out["edge_mult"], out["edge_zkey"], n_nodes, n_edges, status,
                  node_set_offsets=nso, edge_set_offsets=eso)
+
+
+class CapturedBuild:
+    """A build (plain or batched) recorded once into a HIP graph and replayed.
+
+    The library enqueues only kernels and never synchronises or reads device
+    values on the host (grid sizes come from the bounds), so the whole launch
+    sequence of one build can be captured on a stream.  The graph keeps the
+    buffers it was captured with: to build other reads, copy them into
+    ``packed`` / ``offsets`` (same number of bases and reads; for a batched build
+    the same number of sets, new set offsets into ``set_offsets``) and replay.
+    Outputs land in ``out`` and ``result`` as for ``build_async``."""
+
+    def __init__(self, packed, n_bases: int, offsets, k: int, max_keys: int,
+                 set_offsets=None, zkey: bool = True, device="cuda"):
+        self.packed, self.offsets, self.set_offsets = packed, offsets, set_offsets
+        self.n_bases, self.k, self.max_keys = n_bases, k, max_keys
+        n_reads = offsets.numel() - 1
+        n_sets = 1 if set_offsets is None else set_offsets.numel() - 1
+        self.out = alloc_outputs(k, max_keys, max_keys, device, zkey)
+        self.ws = Workspace(n_reads, n_sets, max_keys, k, device)
+        self.result = torch.zeros(3, dtype=torch.int64, device=device)
+        self.node_set_offsets = self.edge_set_offsets = None
+        if set_offsets is not None:
+            self.node_set_offsets = torch.zeros(n_sets + 1, dtype=torch.int64, device=device)
+            self.edge_set_offsets = torch.zeros(n_sets + 1, dtype=torch.int64, device=device)
+        self.graph = torch.cuda.CUDAGraph()
+        self._enqueue()  # one eager build first: every kernel is loaded before capture
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self.graph):
+            self._enqueue()
+        torch.cuda.synchronize()
+
+    def _enqueue(self):
+        build_async(self.packed, self.n_bases, self.offsets, self.k, self.max_keys, self.out,
+                    self.max_keys, self.max_keys, self.result, self.ws,
+                    set_offsets=self.set_offsets, node_set_offsets=self.node_set_offsets,
+                    edge_set_offsets=self.edge_set_offsets)
+
+    def replay(self):
+        """Enqueue one replay on the current stream (no synchronisation)."""
+        self.graph.replay()
+
+    def graph_result(self) -> Graph:
+        """The last replay's tables (synchronises)."""
+        n_nodes, n_edges, status = read_result(self.result)
+        o = self.out
+        g = Graph(self.k, o["node_kmer"], o["node_count"], o["edge_u"], o["edge_v"],
+                  o["edge_orient"], o["edge_mult"], o["edge_zkey"], n_nodes, n_edges, status,
+                  node_set_offsets=self.node_set_offsets, edge_set_offsets=self.edge_set_offsets)
+        g.extra["flags"] = read_flags(self.result)
+        return g
