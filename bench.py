@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--node-route", choices=("auto", "kmers", "endpoints"), default="auto",
                     help="how the node table is built (default: the library's choice)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner on the workload first and time the chosen setting")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -339,6 +341,19 @@ def main():
 
     def step():
         api.build_async(packed, n_bases, offs, k, n_k, out, n_k, n_k, result, ws, stream)
+
+    tuning = None
+    if args.tune:
+        from paper_1003_1940_amd import autotune
+        log("autotuning (every candidate is checked to build identical tables)")
+        tr = autotune.tune(rs.bases, rs.offsets, k, reps=3,
+                           genome_hint=rs.params.get("genome"))
+        api.set_tuning(**tr.best)
+        tuning = {"best": tr.best, "best_ms": round(tr.best_ms, 4),
+                  "default_ms": round(tr.default_ms, 4), "class": tr.input_class,
+                  "candidates": len(tr.timings_ms)}
+        log(f"tuned: {tuning}")
+        torch.cuda.empty_cache()
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -440,6 +455,7 @@ def main():
         "stages_ms": {k_: round(v, 4) for k_, v in stages.items()},
         "sort_reduce_ms": round(sr_ms, 4),
         "build_as_lsd_d8": build_lsd,
+        "tuning": tuning if tuning is not None else api.get_tuning(),
         "h2d_upload_and_pack_s": round(h2d_s, 4),
     }
     print(json.dumps(line), flush=True)

@@ -196,12 +196,20 @@ typedef enum {
 typedef struct {
   int node_path;        /* dbg_node_path; default DBG_NODES_AUTO */
   float endpoint_ratio; /* for DBG_NODES_AUTO; default 0.6 */
-  int reserved[6];      /* zero */
+  /* Shape of the LDS bucket sort: 0 = 512-thread workgroups holding up to 6,144
+   * keys (64-bit; 3,072 for 128-bit keys), one per CU; 1 = 256-thread
+   * workgroups holding half as many, two per CU.  Default 0. */
+  int local_variant;
+  /* Added to the width of the first partition of each batch's distinct keys
+   * (normally log2 of their number, 8 to 11 bits), in [-3, 3].  Default 0. */
+  int lds_digit_bias;
+  int reserved[4];      /* zero */
 } dbg_tuning_t;
 
 /* Process-wide tuning read by every later build call (calls in flight keep the
- * values they started with).  NULL restores the defaults.  Returns DBG_E_ARG
- * for an unknown node_path or a ratio outside [0, 2]. */
+ * values they started with).  NULL restores the defaults.  Every setting gives
+ * the same tables; only the time changes.  Returns DBG_E_ARG for an unknown
+ * node_path or local_variant, a ratio outside [0, 2] or a bias outside [-3, 3]. */
 int dbg_set_tuning(const dbg_tuning_t *tuning);
 /* Copies the current tuning into *tuning (DBG_E_NULL if null). */
 int dbg_get_tuning(dbg_tuning_t *tuning);

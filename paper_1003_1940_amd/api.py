@@ -42,7 +42,11 @@ class _Edges(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("node_path", ctypes.c_int), ("endpoint_ratio", ctypes.c_float),
-                ("reserved", ctypes.c_int * 6)]
+                ("local_variant", ctypes.c_int), ("lds_digit_bias", ctypes.c_int),
+                ("reserved", ctypes.c_int * 4)]
+
+
+TUNING_FIELDS = ("node_path", "endpoint_ratio", "local_variant", "lds_digit_bias")
 
 
 NODES_AUTO, NODES_KMERS, NODES_ENDPOINTS = -1, 0, 1
@@ -81,27 +85,34 @@ def load():
 
 def get_tuning() -> dict:
     """The process-wide build tuning: node_path (NODES_AUTO, NODES_KMERS or
-    NODES_ENDPOINTS) and endpoint_ratio."""
+    NODES_ENDPOINTS), endpoint_ratio, local_variant (0 or 1) and lds_digit_bias."""
     t = _Tuning()
     rc = load().dbg_get_tuning(ctypes.byref(t))
     if rc:
         raise DbgError(rc, "dbg_get_tuning")
-    return {"node_path": t.node_path, "endpoint_ratio": float(t.endpoint_ratio)}
+    return {"node_path": t.node_path, "endpoint_ratio": round(float(t.endpoint_ratio), 6),
+            "local_variant": t.local_variant, "lds_digit_bias": t.lds_digit_bias}
 
 
 def set_tuning(node_path: int | None = None, endpoint_ratio: float | None = None,
+               local_variant: int | None = None, lds_digit_bias: int | None = None,
                defaults: bool = False) -> dict:
     """Change the process-wide tuning (unnamed fields keep their values;
     ``defaults=True`` first restores the library defaults).  Returns the new
-    tuning."""
+    tuning.  Every setting gives identical tables."""
     lib = load()
     if defaults:
         rc = lib.dbg_set_tuning(None)
         if rc:
             raise DbgError(rc, "dbg_set_tuning")
     cur = get_tuning()
-    t = _Tuning(cur["node_path"] if node_path is None else int(node_path),
-                cur["endpoint_ratio"] if endpoint_ratio is None else float(endpoint_ratio))
+    new = dict(node_path=node_path, endpoint_ratio=endpoint_ratio, local_variant=local_variant,
+               lds_digit_bias=lds_digit_bias)
+    for f in TUNING_FIELDS:
+        if new[f] is None:
+            new[f] = cur[f]
+    t = _Tuning(int(new["node_path"]), float(new["endpoint_ratio"]), int(new["local_variant"]),
+                int(new["lds_digit_bias"]))
     rc = lib.dbg_set_tuning(ctypes.byref(t))
     if rc:
         raise DbgError(rc, "dbg_set_tuning")

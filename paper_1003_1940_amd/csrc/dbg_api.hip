@@ -8,7 +8,7 @@ namespace dbg {
 
 // Process-wide tuning: copied under the lock at the start of each build call.
 static std::mutex g_tuning_mu;
-static dbg_tuning_t g_tuning = {DBG_NODES_AUTO, 0.6f, {0, 0, 0, 0, 0, 0}};
+static dbg_tuning_t g_tuning = {DBG_NODES_AUTO, 0.6f, 0, 0, {0, 0, 0, 0}};
 
 static dbg_tuning_t current_tuning() {
   std::lock_guard<std::mutex> lock(g_tuning_mu);
@@ -20,7 +20,9 @@ static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) {
   Layout L{};
   L.key_bytes = k <= 31 ? 8 : 16;
-  const uint64_t cap = k <= 31 ? local_cap<uint64_t, true>() : local_cap<unsigned __int128, true>();
+  // list capacities follow from the smallest batch any workgroup shape takes
+  const uint64_t cap =
+      k <= 31 ? local_cap<uint64_t, true, 1>() : local_cap<unsigned __int128, true, 1>();
   const int edge_bits = 2 * (k + 1);
   const uint64_t levels = (uint64_t)((edge_bits + 7) / 8);  // digit levels incl. level 0
   L.max_tiles = (max_keys + TILE - 1) / TILE + n_sets;
@@ -165,11 +167,14 @@ int dbg_set_stage_events(hipEvent_t *events, int n_events) {
 }
 
 int dbg_set_tuning(const dbg_tuning_t *tuning) {
-  dbg_tuning_t t = {DBG_NODES_AUTO, 0.6f, {0, 0, 0, 0, 0, 0}};
+  dbg_tuning_t t = {DBG_NODES_AUTO, 0.6f, 0, 0, {0, 0, 0, 0}};
   if (tuning) {
     if (tuning->node_path < DBG_NODES_AUTO || tuning->node_path > DBG_NODES_ENDPOINTS)
       return DBG_E_ARG;
     if (!(tuning->endpoint_ratio >= 0.0f && tuning->endpoint_ratio <= 2.0f)) return DBG_E_ARG;
+    if (tuning->local_variant < 0 || tuning->local_variant >= dbg::LOCAL_VARIANTS)
+      return DBG_E_ARG;
+    if (tuning->lds_digit_bias < -3 || tuning->lds_digit_bias > 3) return DBG_E_ARG;
     t = *tuning;
   }
   std::lock_guard<std::mutex> lock(dbg::g_tuning_mu);

@@ -21,35 +21,21 @@ constexpr uint64_t TILE = (uint64_t)STREAM_NT * STREAM_KPT;
 // distinct keys are sorted, and the runs are expanded again.
 // W = true: weighted records (the node table built from edge endpoints), whose
 // 32-bit weights are summed instead of counted; their wider counts take LDS, so
-// the 64-bit variant holds fewer keys.
-template <typename K, bool W = false> struct LocalCfg;
-template <> struct LocalCfg<uint64_t, false> {
-  static constexpr int NT = 512;
-  static constexpr int CAP = 6144;
-  static constexpr int SLOTS = 9216;
-  static constexpr int SMALL = 16;  // segments sorted by one lane's network
+// the 64-bit variant holds fewer keys.  V selects the workgroup shape: 0 = 512
+// threads and the largest batch that fits the 160 KB of LDS (one workgroup per
+// CU), 1 = 256 threads and half the batch (two workgroups per CU: more batches
+// in flight for small inputs, more keys left for deeper partition levels).
+template <typename K, bool W = false, int V = 0> struct LocalCfg {
+  static_assert(V == 0 || V == 1, "two workgroup shapes");
+  static constexpr int NT = V == 0 ? 512 : 256;
+  static constexpr int CAP = (sizeof(K) == 8 ? (W ? 5120 : 6144) : 3072) >> V;
+  static constexpr int SLOTS = CAP * 3 / 2;
+  static constexpr int SMALL = sizeof(K) == 8 ? 16 : 8;  // segments sorted by one lane's network
 };
-template <> struct LocalCfg<uint64_t, true> {
-  static constexpr int NT = 512;
-  static constexpr int CAP = 5120;
-  static constexpr int SLOTS = 7680;
-  static constexpr int SMALL = 16;
-};
-template <> struct LocalCfg<unsigned __int128, false> {
-  static constexpr int NT = 512;
-  static constexpr int CAP = 3072;
-  static constexpr int SLOTS = 4608;
-  static constexpr int SMALL = 8;
-};
-template <> struct LocalCfg<unsigned __int128, true> {
-  static constexpr int NT = 512;
-  static constexpr int CAP = 3072;
-  static constexpr int SLOTS = 4608;
-  static constexpr int SMALL = 8;
-};
-template <typename K, bool W = false> constexpr uint64_t local_cap() {
-  return (uint64_t)LocalCfg<K, W>::CAP;
+template <typename K, bool W = false, int V = 0> constexpr uint64_t local_cap() {
+  return (uint64_t)LocalCfg<K, W, V>::CAP;
 }
+constexpr int LOCAL_VARIANTS = 2;
 
 // Most-significant-digit levels: level 0 is the enumeration scatter; a key of b
 // bits has ceil(b / 8) digits.

@@ -935,9 +935,9 @@ __device__ __forceinline__ uint64_t key_hash(u128 k) {
 // and, at the end, for the expanded keys.
 // Counts of distinct keys: 16 bits suffice for unweighted batches (at most CAP
 // keys); summed record weights (W) take 32.
-template <typename K, bool W>
+template <typename K, bool W, int V>
 struct LocalLds {
-  using Cfg = LocalCfg<K, W>;
+  using Cfg = LocalCfg<K, W, V>;
   using CT = typename std::conditional<W, uint32_t, uint16_t>::type;
   static constexpr int NT = Cfg::NT, NW = NT / 64, CAP = Cfg::CAP;
   static constexpr int SLOTS = Cfg::SLOTS;
@@ -965,11 +965,11 @@ struct LocalLds {
 
 // Finish or enqueue one segment [start, start+c) of distinct keys in buffer `buf`
 // whose keys agree above `shift`.  Called by one lane.
-template <typename K, bool W>
-__device__ __forceinline__ void classify_segment(LocalLds<K, W> &s, uint32_t start, uint32_t c,
-                                                 int shift, uint32_t buf, int nxt) {
-  using CT = typename LocalLds<K, W>::CT;
-  constexpr int SMALL = LocalCfg<K, W>::SMALL;
+template <typename K, bool W, int V>
+__device__ __forceinline__ void classify_segment(LocalLds<K, W, V> &s, uint32_t start,
+                                                 uint32_t c, int shift, uint32_t buf, int nxt) {
+  using CT = typename LocalLds<K, W, V>::CT;
+  constexpr int SMALL = LocalCfg<K, W, V>::SMALL;
   if (c == 0) return;
   K *kb = s.keys_of(buf);
   CT *cb = s.cnts_of(buf);
@@ -1039,17 +1039,19 @@ __device__ __forceinline__ void mark_positions(uint32_t *bits, uint64_t off, uin
 // beside the keys in w0 / w1, are summed per distinct key instead of counting
 // occurrences, and the sum is halved on output (each k-mer occurrence is seen
 // twice).
-template <typename K, bool W>
-__global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
+template <typename K, bool W, int V>
+__global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     const Batch *batches, const uint64_t *n_batches_p, K *b0, K *b1, const uint32_t *w0,
-    const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate) {
-  using Cfg = LocalCfg<K, W>;
-  using CT = typename LocalLds<K, W>::CT;
+    const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate, int dw_bias) {
+  using Cfg = LocalCfg<K, W, V>;
+  using CT = typename LocalLds<K, W, V>::CT;
   constexpr int NT = Cfg::NT, NW = NT / 64, SLOTS = Cfg::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
   constexpr int LPT = (Cfg::CAP + NT - 1) / NT;  // keys per thread
-  static_assert(4 * NT >= 2048, "the first partition uses up to 2048 bins, 4 per thread");
-  __shared__ LocalLds<K, W> s;
+  static_assert(NW * 256 == 4 * NT, "the first partition's bins: 4 per thread");
+  static_assert(4 * NT <= Cfg::CAP, "bucket starts are kept in the distinct-key list");
+  constexpr int MAXDW = NW >= 8 ? 11 : 10;  // log2 of the NW * 256 bins
+  __shared__ LocalLds<K, W, V> s;
   if (ctl->status || gated_off(ctl, gate)) return;
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const uint64_t n_batches = *n_batches_p;
@@ -1173,13 +1175,13 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
     // 3. distinct keys (read from the table into registers through the list of
     //    claimed slots) partitioned by the 8 bits below hb straight into buffer 0
     const uint32_t nu = s.nuniq;
-    // digit width: about one distinct key per bucket, 8 to 11 bits, taken just
-    // below hb
-    int dw = nu <= 256 ? 8 : bit_length((uint64_t)(nu - 1));
-    dw = dw > 11 ? 11 : dw;
+    // digit width: about one distinct key per bucket (shifted by the tuning's
+    // bias), at most MAXDW bits, taken just below hb
+    int dw = (nu <= 256 ? 8 : bit_length((uint64_t)(nu - 1))) + dw_bias;
+    dw = dw < 1 ? 1 : dw > MAXDW ? MAXDW : dw;
     dw = dw > hb ? hb : dw;
     const int dshift = hb - dw;
-    uint32_t *H = &s.hist[0][0];  // NW * 256 = 2048 bins
+    uint32_t *H = &s.hist[0][0];  // NW * 256 bins
     constexpr int UPT = (Cfg::CAP + NT - 1) / NT;
     K uk[UPT];
     uint32_t uc[UPT], ud[UPT];
@@ -1253,7 +1255,7 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
     int cur = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (c4[q] > 64u) classify_segment<K, W>(s, st4[q], c4[q], dshift, 0u, 0);
+      if (c4[q] > 64u) classify_segment<K, W, V>(s, st4[q], c4[q], dshift, 0u, 0);
     while (true) {
       __syncthreads();
       // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
@@ -1318,7 +1320,7 @@ __global__ __launch_bounds__((LocalCfg<K, W>::NT)) void k_local_sort(
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          classify_segment<K, W>(s, base + pre[q], cnt[q], shift - 8, buf ^ 1u, cur ^ 1);
+          classify_segment<K, W, V>(s, base + pre[q], cnt[q], shift - 8, buf ^ 1u, cur ^ 1);
       }
       __syncthreads();
       if (tid == 0) s.nlarge[cur] = 0;
@@ -1661,6 +1663,10 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   const bool two_routes = !edges && S == 1 && A.tuning.node_path != DBG_NODES_KMERS;
   const int g0 = two_routes ? 0 : -1;
   const uint64_t n_words = (A.n_bases + 31) / 32;
+  // workgroup shape of the LDS bucket sort, and the batch capacity it plans for
+  const int lv = A.tuning.local_variant;
+  const uint64_t cap_u = lv == 0 ? local_cap<K, false, 0>() : local_cap<K, false, 1>();
+  const uint64_t cap_w = lv == 0 ? local_cap<K, true, 0>() : local_cap<K, true, 1>();
 
   stage(ev + 0, st);
   hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(1), 0, st, ctl);
@@ -1698,7 +1704,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, ctl, g0);
   hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl, g0);
   PlanArgs pa{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
-              uniform, L.item_cap, ctl, local_cap<K>(), bits, g0};
+              uniform, L.item_cap, ctl, cap_u, bits, g0};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
   const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 2048);
@@ -1712,7 +1718,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la0, x0, x1,
                        ctl);
     PlanArgs pw{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
-                uniform, L.item_cap, ctl, local_cap<K, true>(), bits, 1};
+                uniform, L.item_cap, ctl, cap_w, bits, 1};
     hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
                        pw, la0);
   }
@@ -1731,12 +1737,12 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                  bits, lev, -1};
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
     PlanArgs pl{items[li ^ 1], &ctl->items[li ^ 1], hist[li ^ 1], L.item_cap, batches,
-                L.batch_cap, uniform, L.item_cap, ctl, local_cap<K>(), bits, g0};
+                L.batch_cap, uniform, L.item_cap, ctl, cap_u, bits, g0};
     hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
                        pl, la);
     if (two_routes) {
       PlanArgs pw = pl;
-      pw.local_cap = local_cap<K, true>();
+      pw.local_cap = cap_w;
       pw.gate = 1;
       hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0,
                          st, pw, la);
@@ -1753,13 +1759,24 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   stage(ev + 5, st);
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.rle_tiles * (TILE / 64), 256, 8192)), dim3(256), 0,
                      st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
-  hipLaunchKernelGGL((k_local_sort<K, false>), dim3(grid_for(L.batch_cap, 1, 2048)),
-                     dim3(LocalCfg<K>::NT), 0, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
-                     runbits, ctl, g0);
-  if (two_routes)
-    hipLaunchKernelGGL((k_local_sort<K, true>), dim3(grid_for(L.batch_cap, 1, 2048)),
-                       dim3(LocalCfg<K, true>::NT), 0, st, batches, &ctl->n_batches, x0, x1, wt0,
-                       wt1, runbits, ctl, 1);
+  const int bias = A.tuning.lds_digit_bias;
+  if (lv == 0) {
+    hipLaunchKernelGGL((k_local_sort<K, false, 0>), dim3(grid_for(L.batch_cap, 1, 2048)),
+                       dim3(LocalCfg<K, false, 0>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
+                       wt0, wt1, runbits, ctl, g0, bias);
+    if (two_routes)
+      hipLaunchKernelGGL((k_local_sort<K, true, 0>), dim3(grid_for(L.batch_cap, 1, 2048)),
+                         dim3(LocalCfg<K, true, 0>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
+                         wt0, wt1, runbits, ctl, 1, bias);
+  } else {
+    hipLaunchKernelGGL((k_local_sort<K, false, 1>), dim3(grid_for(L.batch_cap, 1, 4096)),
+                       dim3(LocalCfg<K, false, 1>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
+                       wt0, wt1, runbits, ctl, g0, bias);
+    if (two_routes)
+      hipLaunchKernelGGL((k_local_sort<K, true, 1>), dim3(grid_for(L.batch_cap, 1, 4096)),
+                         dim3(LocalCfg<K, true, 1>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
+                         wt0, wt1, runbits, ctl, 1, bias);
+  }
   stage(ev + 6, st);
   hipLaunchKernelGGL(k_uniform_emit<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
                      x1, runbits, ctl, g0);

@@ -96,3 +96,22 @@ def test_batched_graph_replays():
         assert torch.equal(g.edge_set_offsets, eager.edge_set_offsets)
         y = torch.ones(1000, device="cuda").cumsum(0)
         assert float(y[-1].item()) == 1000.0
+
+
+def test_autotune_settings_agree():
+    """Every tuning candidate builds identical tables (the tuner checks this
+    itself and raises otherwise); the endpoint candidates take that route on a
+    high-coverage input, and the choice is one of the candidates."""
+    from paper_1003_1940_amd import api, autotune
+    rng = np.random.default_rng(77)
+    g = synth.random_genome(rng, 20_000)
+    rs = synth.sample_reads(rng, g, 4000, 100, 0.001)
+    for k in (31, 63):
+        say(f"[gpu-graph] autotune k={k}")
+        r = autotune.tune(rs.bases, rs.offsets, k, reps=1)
+        assert len(r.timings_ms) == 12
+        assert r.best in [s for s, _, _ in r.timings_ms]
+        for s, _, took in r.timings_ms:
+            assert took == (s["node_path"] == api.NODES_ENDPOINTS), s
+    assert api.get_tuning() == {"node_path": api.NODES_AUTO, "endpoint_ratio": pytest.approx(0.6),
+                                "local_variant": 0, "lds_digit_bias": 0}
