@@ -289,11 +289,20 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--node-route", choices=("auto", "kmers", "endpoints"), default="auto",
                     help="how the node table is built (default: the library's choice)")
+    ap.add_argument("--cap-frac", type=float, default=None,
+                    help="output rows as a fraction of the k-mer positions (default 1; 0.55 "
+                         "without edge keys for the full-size k=63 workload, which needs it "
+                         "to fit 288 GB)")
+    ap.add_argument("--no-zkey", action="store_true", help="do not export edge (k+1)-mer keys")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on the workload first and time the chosen setting")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
+    if args.cap_frac is None:
+        big = args.workload == "plain_large_k63" and args.scale > 0.5
+        args.cap_frac = 0.55 if big else 1.0
+        args.no_zkey = args.no_zkey or big
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is described in DESIGN.md and not implemented.",
@@ -318,7 +327,9 @@ def main():
                                   "endpoints": api.NODES_ENDPOINTS}[args.node_route])
     gen_name, k = WORKLOADS[args.workload]
     log(f"generating {args.workload} (scale {args.scale})")
-    rs = getattr(synth, gen_name)(scale=args.scale)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    gen = getattr(synth, gen_name)
+    rs = gen(scale=args.scale, workers=workers) if gen_name == "plain_large" else gen(scale=args.scale)
     n_reads, n_bases = rs.n_reads, rs.n_bases
     n_k = rs.kmer_count(k)
     n_e = rs.kmer_count(k + 1)
@@ -331,7 +342,11 @@ def main():
     packed, offs, _ = api.upload(rs.bases, rs.offsets, dev)
     torch.cuda.synchronize()
     h2d_s = time.perf_counter() - t0
-    out = api.alloc_outputs(k, n_k, n_k, dev, zkey=True)
+    # output capacity: one row per k-mer position unless --cap-frac lowers it
+    # (memory-tight mode: the build reports DBG_E_CAPACITY if it was too low)
+    cap = max(1, int(n_k * args.cap_frac))
+    zkey = not args.no_zkey
+    out = api.alloc_outputs(k, cap, cap, dev, zkey=zkey)
     ws = api.Workspace(n_reads, 1, n_k, k, dev)
     result = torch.zeros(3, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
@@ -340,7 +355,7 @@ def main():
     lib.dbg_set_stage_events.argtypes = [ctypes.c_void_p, ctypes.c_int]
 
     def step():
-        api.build_async(packed, n_bases, offs, k, n_k, out, n_k, n_k, result, ws, stream)
+        api.build_async(packed, n_bases, offs, k, n_k, out, cap, cap, result, ws, stream)
 
     tuning = None
     if args.tune:
@@ -398,7 +413,7 @@ def main():
     log("stages (ms): " + ", ".join(f"{k_}={v:.3f}" for k_, v in stages.items()))
 
     # dominant single-kernel stage and its roofline
-    row_bytes = {"edges": 3 * w + 5, "nodes": w + 4}
+    row_bytes = {"edges": (3 if zkey else 2) * w + 5, "nodes": w + 4}
     uniq = {"edges": n_edges, "nodes": n_nodes}
     keys = {"edges": n_e, "nodes": n_k}
     best = None
@@ -449,7 +464,7 @@ def main():
         "config": {"workload": args.workload, "reads": n_reads, "read_len": rs.params.get("read_len"),
                    "k": k, "genome": rs.params.get("genome"), "kmers": n_k, "kplus1mers": n_e,
                    "nodes": n_nodes, "edges": n_edges, "scale": args.scale,
-                   "node_route": node_route},
+                   "node_route": node_route, "output_rows": cap, "edge_zkey": zkey},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms": {k_: round(v, 4) for k_, v in stages.items()},

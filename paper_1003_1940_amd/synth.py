@@ -159,15 +159,57 @@ def plain_repeats(scale: float = 1.0) -> ReadSet:
     return rs
 
 
-def plain_large(scale: float = 1.0) -> ReadSet:
+READ_CHUNK = 1 << 20  # reads drawn per independent seed in the chunked sampler
+
+_shared = {}
+
+
+def _fill_chunk(ci):
+    """Worker: reads of chunk ci into the shared output (forked processes)."""
+    sh = _shared
+    r0 = ci * READ_CHUNK
+    r1 = min(sh["n"], r0 + READ_CHUNK)
+    rs = sample_reads(np.random.default_rng(sh["seeds"][ci]), sh["genome"], r1 - r0, sh["L"],
+                      sh["err"])
+    sh["out"][r0 * sh["L"]:r1 * sh["L"]] = rs.bases
+    return ci
+
+
+def sample_reads_chunked(seed: int, genome: np.ndarray, n_reads: int, read_len: int,
+                         err: float, workers: int = 1) -> ReadSet:
+    """Fixed-length reads drawn in chunks of READ_CHUNK reads, chunk i from its own
+    seed (SeedSequence(seed).spawn), so the result does not depend on
+    ``workers``; with workers > 1 the chunks are drawn by forked processes into
+    one shared buffer (fork before the process touches a GPU)."""
+    import mmap
+    L = int(read_len)
+    n_chunks = (n_reads + READ_CHUNK - 1) // READ_CHUNK
+    seeds = np.random.SeedSequence(seed).spawn(n_chunks)
+    buf = mmap.mmap(-1, max(1, n_reads * L))
+    out = np.frombuffer(buf, dtype=np.uint8, count=n_reads * L)
+    _shared.update(n=n_reads, L=L, err=err, genome=genome, seeds=seeds, out=out)
+    try:
+        _map(_fill_chunk, list(range(n_chunks)), workers)
+        bases = out.copy()
+    finally:
+        _shared.clear()
+        del out
+        buf.close()
+    offsets = np.arange(n_reads + 1, dtype=np.uint64) * np.uint64(L)
+    return ReadSet(bases, offsets)
+
+
+def plain_large(scale: float = 1.0, workers: int = 1) -> ReadSet:
     """Plain build, k = 63: 100,000,000-base genome with GC content 0.41;
     40,000,000 reads of length 150 (60x), strand p = 0.5, 1% errors.  ``scale``
-    shrinks the genome and the read count together (coverage stays 60x)."""
+    shrinks the genome and the read count together (coverage stays 60x).  Reads
+    are drawn in chunks of independent seeds (``workers`` processes may draw
+    them; the reads are the same for any count)."""
     rng = np.random.default_rng(SEED_BASE + 2)
     G = max(1000, int(100_000_000 * scale))
     g = random_genome(rng, G, gc=0.41)
     n = max(1, int(40_000_000 * scale))
-    rs = sample_reads(rng, g, n, 150, 0.01)
+    rs = sample_reads_chunked(SEED_BASE + 20, g, n, 150, 0.01, workers)
     rs.params = dict(workload="plain_large_k63", genome=G, reads=n, read_len=150, err=0.01,
                      gc=0.41, seed=SEED_BASE + 2)
     return rs
