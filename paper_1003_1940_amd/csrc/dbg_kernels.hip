@@ -488,7 +488,10 @@ __global__ __launch_bounds__(256) void k_col_apply(uint32_t *thist, const uint32
 // parent.  Every thread of the workgroup must call it.
 template <typename K, bool W = false>
 struct PartLds {
-  K keys[TILE];
+  union {
+    K keys[TILE];
+    EnumLds stage;  // the enumeration's staged words, dead once its keys are in registers
+  };
   uint32_t wts[W ? TILE : 1];  // record weights (W), moved with their keys
   uint64_t gbase[256];
   uint32_t cnt[256];
@@ -546,12 +549,13 @@ template <typename K>
 __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const uint64_t *cursor0,
                                                             const uint32_t *tpre, K *dst,
                                                             const Ctl *ctl) {
+  // the staged words share LDS with the partition's key buffer: partition_tile
+  // passes a barrier before it writes keys, after every thread has enumerated
   __shared__ PartLds<K> s;
-  __shared__ EnumLds L;
   const uint64_t t = blockIdx.x;
   if (ctl->status || gated_off(ctl, a.gate) || t >= ctl->n_tiles) return;
   const TileRange tr = enum_tile(a, t);
-  const TileSrc ts = stage_tile(a, tr, L);
+  const TileSrc ts = stage_tile(a, tr, s.stage);
   K keys[STREAM_KPT];
   const int n = enum_keys<K, STREAM_KPT>(a, ts, tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
                                          tr.end, tr.read_lo, tr.read_hi, keys);
@@ -1489,31 +1493,37 @@ struct OutArgs {
   int k;
 };
 
+// Two threads per bitmap word (16 positions each): the LDS staging of a tile
+// allows three workgroups per CU, so 256 threads give twice the waves of one
+// thread per word.
+constexpr int EMIT_WNT = 2 * EMIT_NT;
+
 template <typename K, bool EDGES>
-__global__ __launch_bounds__(EMIT_NT) void k_emit_write(const uint32_t *bits,
-                                                        const uint64_t *tile_base, const K *b0,
-                                                        const K *b1, OutArgs o, const Ctl *ctl) {
+__global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
+                                                         const uint64_t *tile_base, const K *b0,
+                                                         const K *b1, OutArgs o, const Ctl *ctl) {
   // gather the tile's distinct keys and counts in order into LDS, then write
   // the output rows with consecutive threads on consecutive rows
   __shared__ K sk[TILE];
   __shared__ uint32_t sc[TILE];
-  __shared__ uint64_t wsum[EMIT_NT / 64 + 1];
+  __shared__ uint64_t wsum[EMIT_WNT / 64 + 1];
   if (ctl->status) return;
-  const uint64_t wi = blockIdx.x * (uint64_t)EMIT_NT + threadIdx.x;
-  uint32_t word = bits[wi];
+  const uint64_t wi = blockIdx.x * (uint64_t)EMIT_NT + (threadIdx.x >> 1);
+  const uint32_t half = (threadIdx.x & 1u) * 16u;
+  uint32_t word = (bits[wi] >> half) & 0xffffu;
   uint64_t tot;
-  uint32_t r = (uint32_t)block_exclusive_scan<EMIT_NT>((uint64_t)__popc(word), wsum, &tot);
+  uint32_t r = (uint32_t)block_exclusive_scan<EMIT_WNT>((uint64_t)__popc(word), wsum, &tot);
   while (word) {
     const int b = __ffs(word) - 1;
     word &= word - 1;
-    const uint64_t pos = (wi << 5) + (uint64_t)b;
+    const uint64_t pos = (wi << 5) + half + (uint64_t)b;
     sk[r] = b0[pos];
     sc[r] = (uint32_t)b1[pos];
     ++r;
   }
   __syncthreads();
   const uint64_t base = tile_base[blockIdx.x];
-  for (uint32_t i = threadIdx.x; i < (uint32_t)tot; i += EMIT_NT) {
+  for (uint32_t i = threadIdx.x; i < (uint32_t)tot; i += EMIT_WNT) {
     const uint64_t j = base + i;
     if (j >= o.capacity) break;
     const K key = sk[i];
@@ -1707,7 +1717,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
               uniform, L.item_cap, ctl, cap_u, bits, g0};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
-  const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 2048);
+  const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 8192);
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
   LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], cursor, wt0, wt1,
                 bits, 0, 1};
@@ -1761,19 +1771,19 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                      st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
   const int bias = A.tuning.lds_digit_bias;
   if (lv == 0) {
-    hipLaunchKernelGGL((k_local_sort<K, false, 0>), dim3(grid_for(L.batch_cap, 1, 2048)),
+    hipLaunchKernelGGL((k_local_sort<K, false, 0>), dim3(grid_for(L.batch_cap, 1, 256)),
                        dim3(LocalCfg<K, false, 0>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
                        wt0, wt1, runbits, ctl, g0, bias);
     if (two_routes)
-      hipLaunchKernelGGL((k_local_sort<K, true, 0>), dim3(grid_for(L.batch_cap, 1, 2048)),
+      hipLaunchKernelGGL((k_local_sort<K, true, 0>), dim3(grid_for(L.batch_cap, 1, 256)),
                          dim3(LocalCfg<K, true, 0>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
                          wt0, wt1, runbits, ctl, 1, bias);
   } else {
-    hipLaunchKernelGGL((k_local_sort<K, false, 1>), dim3(grid_for(L.batch_cap, 1, 4096)),
+    hipLaunchKernelGGL((k_local_sort<K, false, 1>), dim3(grid_for(L.batch_cap, 1, 512)),
                        dim3(LocalCfg<K, false, 1>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
                        wt0, wt1, runbits, ctl, g0, bias);
     if (two_routes)
-      hipLaunchKernelGGL((k_local_sort<K, true, 1>), dim3(grid_for(L.batch_cap, 1, 4096)),
+      hipLaunchKernelGGL((k_local_sort<K, true, 1>), dim3(grid_for(L.batch_cap, 1, 512)),
                          dim3(LocalCfg<K, true, 1>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
                          wt0, wt1, runbits, ctl, 1, bias);
   }
@@ -1800,14 +1810,14 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     oa.count = A.edges.mult;
     oa.capacity = capacity = A.edges.capacity;
     set_rows = A.edge_set_offsets;
-    hipLaunchKernelGGL((k_emit_write<K, true>), dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st,
+    hipLaunchKernelGGL((k_emit_write<K, true>), dim3((unsigned)L.rle_tiles), dim3(EMIT_WNT), 0, st,
                        runbits, rle_heads, x0, x1, oa, ctl);
   } else {
     oa.kmer = A.nodes.kmer;
     oa.count = A.nodes.count;
     oa.capacity = capacity = A.nodes.capacity;
     set_rows = A.node_set_offsets;
-    hipLaunchKernelGGL((k_emit_write<K, false>), dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st,
+    hipLaunchKernelGGL((k_emit_write<K, false>), dim3((unsigned)L.rle_tiles), dim3(EMIT_WNT), 0, st,
                        runbits, rle_heads, x0, x1, oa, ctl);
   }
   stage(ev + 8, st);
