@@ -1125,7 +1125,8 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     // 2. count duplicates in an LDS hash table keyed by the first occurrence
     {
       // first probe of every key of this thread at once (independent LDS
-      // atomics in flight), then linear probing for the few that collided
+      // atomics in flight), then the keys that own the probed slots (again all
+      // at once), then linear probing for the few that collided
       uint32_t hs[LPT], os[LPT];
 #pragma unroll
       for (int j = 0; j < LPT; ++j) {
@@ -1137,31 +1138,39 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
           os[j] = atomicCAS(&own[hs[j]], EMPTY, e);
         }
       }
+      bool same[LPT];
+#pragma unroll
+      for (int j = 0; j < LPT; ++j) same[j] = os[j] == EMPTY || s.key0[os[j]] == pre[j];
+      uint32_t claimed = 0, ncl = 0;  // bit j: this thread's key j claimed slot hs[j]
 #pragma unroll
       for (int j = 0; j < LPT; ++j) {
         const uint32_t e = tid + (uint32_t)j * NT;
-        bool claimed = false;
-        uint32_t h = hs[j];
         if (e < m) {
-          const K key = pre[j];
-          uint32_t o = os[j];
-          while (o != EMPTY && s.key0[o] != key) {
-            h = h + 1 == (uint32_t)SLOTS ? 0u : h + 1;
-            o = atomicCAS(&own[h], EMPTY, e);
+          uint32_t h = hs[j], o = os[j];
+          if (!same[j]) {
+            const K key = pre[j];
+            do {
+              h = h + 1 == (uint32_t)SLOTS ? 0u : h + 1;
+              o = atomicCAS(&own[h], EMPTY, e);
+            } while (o != EMPTY && s.key0[o] != key);
+            hs[j] = h;
           }
-          claimed = o == EMPTY;
+          if (o == EMPTY) {
+            claimed |= 1u << j;
+            ++ncl;
+          }
           atomicAdd(&tcnt[h], W ? prew[j] : 1u);
         }
-        // the lane that claimed a slot records it: one LDS atomic per wave
-        const uint64_t cm = __ballot(claimed);
-        if (cm) {
-          uint32_t base = 0;
-          if (lane == (uint32_t)(__ffsll((long long)cm) - 1))
-            base = atomicAdd(&s.nuniq, (uint32_t)__popcll(cm));
-          base = __shfl(base, __ffsll((long long)cm) - 1, 64);
-          if (claimed) s.ulist[base + (uint32_t)__popcll(cm & lanemask_lt())] = (uint16_t)h;
-        }
       }
+      // record the claimed slots: one LDS atomic per wave
+      const uint32_t incl = wave_inclusive_scan(ncl);
+      const uint32_t wtot = __shfl(incl, 63, 64);
+      uint32_t base = 0;
+      if (lane == 0 && wtot) base = atomicAdd(&s.nuniq, wtot);
+      base = __shfl(base, 0, 64) + incl - ncl;
+#pragma unroll
+      for (int j = 0; j < LPT; ++j)
+        if (claimed & (1u << j)) s.ulist[base++] = (uint16_t)hs[j];
     }
     __syncthreads();
     // the next batch's keys load while this one is sorted (descriptors are read
