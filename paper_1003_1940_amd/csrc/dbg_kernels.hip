@@ -1081,7 +1081,11 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
       }
     }
   };
-  if (tid == 0) s.dirty = 1;  // the table starts uninitialised
+  if (tid == 0) {
+    s.dirty = 1;  // the table starts uninitialised
+    s.nuniq = s.nmid = 0;
+    s.nlarge[0] = s.nlarge[1] = 0;
+  }
   __syncthreads();
   const Batch none = {0, 0, 0};
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
@@ -1113,15 +1117,11 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
         tcnt[q] = 0;
       }
     }
-    __syncthreads();
-    if (tid == 0) {
-      s.nlarge[0] = s.nlarge[1] = 0;
-      s.nmid = 0;
-      s.nuniq = 0;
-      s.dirty = 0;
-    }
+    // the piece lists are empty and the distinct-key counter is zero here: both
+    // are left so by the previous batch
     for (uint32_t q = tid; q < (uint32_t)(NW * 256); q += NT) s.hist[0][q] = 0;
     __syncthreads();
+    if (tid == 0) s.dirty = 0;
     // 2. count duplicates in an LDS hash table keyed by the first occurrence
     {
       // first probe of every key of this thread at once (independent LDS
@@ -1215,6 +1215,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
       }
     }
     __syncthreads();
+    if (tid == 0) s.nuniq = 0;  // every thread holds nu; ready for the next batch
     // thread t owns bins 4t .. 4t+3
     uint32_t c4[4], st4[4], sum4 = 0;
 #pragma unroll
@@ -1265,12 +1266,13 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
         s.key0[fin[j]] = uk[j];
         s.cnt0[fin[j]] = (CT)uc[j];
       }
-    int cur = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (c4[q] > 64u) classify_segment<K, W, V>(s, st4[q], c4[q], dshift, 0u, 0);
-    while (true) {
-      __syncthreads();
+    __syncthreads();
+    // pieces left over (usually none): refined until every piece is finished
+    int cur = 0;
+    while (s.nmid != 0 || s.nlarge[cur] != 0) {
       // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
       for (uint32_t i = w; i < s.nmid; i += NW) {
         const uint64_t d = s.mid[i];
@@ -1338,8 +1340,8 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
       __syncthreads();
       if (tid == 0) s.nlarge[cur] = 0;
       cur ^= 1;
+      __syncthreads();
     }
-    __syncthreads();
     // 4. the batch's distinct keys, sorted, replace its first positions in
     //    buffer 0, their counts go to the same positions of buffer 1, and the
     //    bitmap marks those positions
