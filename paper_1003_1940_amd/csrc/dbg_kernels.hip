@@ -1504,41 +1504,45 @@ struct OutArgs {
   int k;
 };
 
-// Two threads per bitmap word (16 positions each): the LDS staging of a tile
-// allows three workgroups per CU, so 256 threads give twice the waves of one
-// thread per word.
-constexpr int EMIT_WNT = 2 * EMIT_NT;
+// One thread per output row: row i of a tile is the i-th marked position, found
+// from the tile's 128 word popcount prefixes (kept in LDS) by a binary search
+// and a bit select, so consecutive threads read consecutive distinct keys and
+// write consecutive rows with no staging of the keys themselves.
+constexpr int EMIT_WNT = 256;
 
 template <typename K, bool EDGES>
 __global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
                                                          const uint64_t *tile_base, const K *b0,
                                                          const K *b1, OutArgs o, const Ctl *ctl) {
-  // gather the tile's distinct keys and counts in order into LDS, then write
-  // the output rows with consecutive threads on consecutive rows
-  __shared__ K sk[TILE];
-  __shared__ uint32_t sc[TILE];
+  __shared__ uint32_t wpre[EMIT_NT + 1];  // marked positions before each word of the tile
+  __shared__ uint32_t wbits[EMIT_NT];
   __shared__ uint64_t wsum[EMIT_WNT / 64 + 1];
   if (ctl->status) return;
-  const uint64_t wi = blockIdx.x * (uint64_t)EMIT_NT + (threadIdx.x >> 1);
-  const uint32_t half = (threadIdx.x & 1u) * 16u;
-  uint32_t word = (bits[wi] >> half) & 0xffffu;
+  const uint64_t w0 = blockIdx.x * (uint64_t)EMIT_NT;
+  const uint32_t word = threadIdx.x < (uint32_t)EMIT_NT ? bits[w0 + threadIdx.x] : 0u;
   uint64_t tot;
-  uint32_t r = (uint32_t)block_exclusive_scan<EMIT_WNT>((uint64_t)__popc(word), wsum, &tot);
-  while (word) {
-    const int b = __ffs(word) - 1;
-    word &= word - 1;
-    const uint64_t pos = (wi << 5) + half + (uint64_t)b;
-    sk[r] = b0[pos];
-    sc[r] = (uint32_t)b1[pos];
-    ++r;
+  const uint32_t ex = (uint32_t)block_exclusive_scan<EMIT_WNT>((uint64_t)__popc(word), wsum, &tot);
+  if (threadIdx.x < (uint32_t)EMIT_NT) {
+    wpre[threadIdx.x] = ex;
+    wbits[threadIdx.x] = word;
   }
+  if (threadIdx.x == 0) wpre[EMIT_NT] = (uint32_t)tot;
   __syncthreads();
   const uint64_t base = tile_base[blockIdx.x];
   for (uint32_t i = threadIdx.x; i < (uint32_t)tot; i += EMIT_WNT) {
+    uint32_t lo = 0, hi = EMIT_NT;  // the last word w with wpre[w] <= i
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (wpre[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    uint32_t wd = wbits[lo];
+    for (uint32_t r = i - wpre[lo]; r; --r) wd &= wd - 1;  // drop the lower marked bits
+    const uint64_t pos = ((w0 + lo) << 5) + (uint64_t)(__ffs(wd) - 1);
     const uint64_t j = base + i;
     if (j >= o.capacity) break;
-    const K key = sk[i];
-    o.count[j] = sc[i];
+    const K key = b0[pos];
+    o.count[j] = (uint32_t)b1[pos];
     if (EDGES) {
       K u, v;
       uint32_t orient;
