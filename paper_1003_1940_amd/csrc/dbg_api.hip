@@ -46,8 +46,11 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) 
   L.set_tbase = take((n_sets + 1) * sizeof(uint64_t));
   L.tile_read = take(L.max_tiles * sizeof(uint64_t));
   L.tile_set = take(L.max_tiles * sizeof(uint32_t));
-  L.thist = take((L.max_tiles + 1) * 256 * sizeof(uint32_t));
-  L.csum = take(((L.max_tiles + 63) / 64 + 1) * 256 * sizeof(uint32_t));
+  // per-tile digit counts: enumeration tiles, or the tiles of a partition level
+  // (at most one partial tile per bucket more)
+  const uint64_t rows = L.max_tiles + L.item_cap;
+  L.thist = take((rows + 1) * 256 * sizeof(uint32_t));
+  L.csum = take(((rows + 63) / 64 + 1) * 256 * sizeof(uint32_t));
   L.cursor0 = take(n_sets * 256 * sizeof(uint64_t));
   for (int i = 0; i < 2; ++i) L.items[i] = take(L.item_cap * sizeof(Item));
   for (int i = 0; i < 2; ++i) L.hist[i] = take(L.item_cap * 256 * sizeof(uint64_t));

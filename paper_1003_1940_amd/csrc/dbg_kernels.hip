@@ -408,9 +408,10 @@ constexpr uint64_t COL_CHUNK = 128;
 constexpr int COL_BATCH = 16;  // independent loads in flight per thread
 
 __global__ __launch_bounds__(256) void k_col_reduce(const uint32_t *thist, uint32_t *csum,
-                                                    const Ctl *ctl, int gate) {
+                                                    const uint64_t *n_tiles_p, const Ctl *ctl,
+                                                    int gate) {
   if (ctl->status || gated_off(ctl, gate)) return;
-  const uint64_t nt = ctl->n_tiles;
+  const uint64_t nt = *n_tiles_p;
   const uint64_t t0 = blockIdx.x * COL_CHUNK;
   if (t0 >= nt) return;
   const uint64_t t1 = t0 + COL_CHUNK < nt ? t0 + COL_CHUNK : nt;
@@ -426,10 +427,11 @@ __global__ __launch_bounds__(256) void k_col_reduce(const uint32_t *thist, uint3
 }
 
 // One workgroup of 1024 threads: column d = tid % 256 is scanned in four parts.
-__global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const Ctl *ctl, int gate) {
+__global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const uint64_t *n_tiles_p,
+                                                  const Ctl *ctl, int gate) {
   __shared__ uint32_t part[4][256];
   if (ctl->status || gated_off(ctl, gate)) return;
-  const uint64_t nc = (ctl->n_tiles + COL_CHUNK - 1) / COL_CHUNK;
+  const uint64_t nc = (*n_tiles_p + COL_CHUNK - 1) / COL_CHUNK;
   const uint32_t d = threadIdx.x & 255, pi = threadIdx.x >> 8;
   const uint64_t q = (nc + 3) / 4;
   const uint64_t c0 = pi * q, c1 = c0 + q < nc ? c0 + q : nc;
@@ -459,9 +461,10 @@ __global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const Ctl *ct
 }
 
 __global__ __launch_bounds__(256) void k_col_apply(uint32_t *thist, const uint32_t *csum,
-                                                   const Ctl *ctl, int gate) {
+                                                   const uint64_t *n_tiles_p, const Ctl *ctl,
+                                                   int gate) {
   if (ctl->status || gated_off(ctl, gate)) return;
-  const uint64_t nt = ctl->n_tiles;
+  const uint64_t nt = *n_tiles_p;
   const uint64_t t0 = blockIdx.x * COL_CHUNK;
   if (t0 >= nt && !(t0 == 0 && nt == 0)) return;
   const uint64_t t1 = t0 + COL_CHUNK < nt ? t0 + COL_CHUNK : nt;
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
 struct PlanArgs {
   Item *next_items;       // list receiving oversized buckets
   uint64_t *next_count;   // its counter in Ctl
-  uint64_t *next_hist;    // histogram rows of that list (zeroed here)
+  uint64_t *next_hist;    // histogram rows of that list (zeroed here; null: none kept)
   uint64_t item_cap;
   Batch *batches;
   uint64_t batch_cap;
@@ -655,7 +658,8 @@ __device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint3
       const uint64_t ii = s.base[1] + lid;
       if (ii < p.item_cap) {
         p.next_items[ii] = Item{off + ex, c, 0, src, 0};
-        for (int j = 0; j < 256; ++j) p.next_hist[ii * 256 + j] = 0;
+        if (p.next_hist)
+          for (int j = 0; j < 256; ++j) p.next_hist[ii * 256 + j] = 0;
       } else {
         set_status(p.ctl, DBG_E_INTERNAL);
       }
@@ -712,13 +716,24 @@ struct LevelArgs {
   const Item *items;
   const uint64_t *n_items_p;
   const uint64_t *n_tiles_p;
-  uint64_t *hist;
+  uint64_t *hist;     // per-item digit counts (atomic mode)
+  uint32_t *tpre;     // per-tile digit counts, then their column prefix (tile mode), or null
   uint64_t *cursor;
   uint32_t *w0, *w1;  // record weights beside buffers 0 and 1 (weighted scatter)
   int bits;
   int level;
   int gate;
 };
+
+// Tile mode (a level with one large bucket, whose 256 counters every tile would
+// otherwise hit with atomics): every tile writes its 256 digit counts to a row, a
+// column prefix over the rows gives each tile the exact offset of each digit
+// within its bucket, and the scatter needs no atomics.  Atomic mode (levels with
+// many buckets): counts and cursors are reserved with global atomics.
+__device__ __forceinline__ uint64_t item_end_tile(const Item *items, uint64_t ii, uint64_t n_items,
+                                                  uint64_t n_tiles) {
+  return ii + 1 < n_items ? items[ii + 1].tbase : n_tiles;
+}
 
 __device__ __forceinline__ uint64_t find_item(const Item *items, uint64_t n, uint64_t t) {
   uint64_t lo = 0, hi = n;  // last item with tbase <= t
@@ -766,7 +781,8 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K 
       if (r < n) atomicAdd(&h[msd_digit(keys[r], a.bits, a.level)], 1u);
     __syncthreads();
     const uint32_t c = h[threadIdx.x];
-    if (c) atomicAdd((unsigned long long *)&a.hist[ii * 256 + threadIdx.x], (unsigned long long)c);
+    if (a.tpre) a.tpre[t * 256 + threadIdx.x] = c;
+    else if (c) atomicAdd((unsigned long long *)&a.hist[ii * 256 + threadIdx.x], (unsigned long long)c);
     __syncthreads();
   }
 }
@@ -777,8 +793,14 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_plan(PlanArgs p, LevelArgs 
   const uint64_t n_items = *a.n_items_p;
   for (uint64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
     const Item it = a.items[ii];
-    plan_children(p, a.hist[ii * 256 + threadIdx.x], it.off, 1u - it.src, a.level + 1,
-                  a.cursor + ii * 256, lds);
+    uint64_t c;
+    if (a.tpre) {
+      const uint64_t t1 = item_end_tile(a.items, ii, n_items, *a.n_tiles_p);
+      c = (uint32_t)(a.tpre[t1 * 256 + threadIdx.x] - a.tpre[it.tbase * 256 + threadIdx.x]);
+    } else {
+      c = a.hist[ii * 256 + threadIdx.x];
+    }
+    plan_children(p, c, it.off, 1u - it.src, a.level + 1, a.cursor + ii * 256, lds);
   }
 }
 
@@ -799,7 +821,14 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0,
     const int n = load_tile<K>(it.src ? b1 : b0, start, end, keys);
     uint32_t wts[STREAM_KPT] = {};
     if (W) load_tile<uint32_t>(it.src ? a.w1 : a.w0, start, end, wts);
-    partition_tile<K, W>(keys, wts, n, a.bits, a.level, a.cursor + ii * 256, 0, it.src ? b0 : b1,
+    uint64_t *cur = a.cursor + ii * 256;
+    uint64_t my_base = 0;
+    if (a.tpre) {  // column prefixes are counted modulo 2^32 (a table has < 2^32 keys)
+      const uint32_t d = threadIdx.x;
+      my_base = cur[d] + (uint32_t)(a.tpre[t * 256 + d] - a.tpre[it.tbase * 256 + d]);
+      cur = nullptr;
+    }
+    partition_tile<K, W>(keys, wts, n, a.bits, a.level, cur, my_base, it.src ? b0 : b1,
                          it.src ? a.w0 : a.w1, s);
   }
 }
@@ -1725,23 +1754,36 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   }
   stage(ev + 2, st);
   const unsigned col_chunks = (unsigned)((L.max_tiles + COL_CHUNK - 1) / COL_CHUNK);
-  hipLaunchKernelGGL(k_col_reduce, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl, g0);
-  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, ctl, g0);
-  hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum, ctl, g0);
+  hipLaunchKernelGGL(k_col_reduce, dim3(col_chunks), dim3(256), 0, st, thist, csum,
+                     &ctl->n_tiles, ctl, g0);
+  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, &ctl->n_tiles, ctl, g0);
+  hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum,
+                     &ctl->n_tiles, ctl, g0);
+  // column prefix of the per-tile digit counts of a level in tile mode
+  const unsigned lcol_chunks =
+      (unsigned)((L.max_tiles + L.item_cap + COL_CHUNK - 1) / COL_CHUNK);
+  auto level_prefix = [&](const uint64_t *n_tiles_p, int gate) {
+    hipLaunchKernelGGL(k_col_reduce, dim3(lcol_chunks), dim3(256), 0, st, thist, csum, n_tiles_p,
+                       ctl, gate);
+    hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, n_tiles_p, ctl, gate);
+    hipLaunchKernelGGL(k_col_apply, dim3(lcol_chunks), dim3(256), 0, st, thist, csum, n_tiles_p,
+                       ctl, gate);
+  };
   PlanArgs pa{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
               uniform, L.item_cap, ctl, cap_u, bits, g0};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
   const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 8192);
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
-  LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], cursor, wt0, wt1,
-                bits, 0, 1};
+  LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], thist, cursor, wt0,
+                wt1, bits, 0, 1};
   if (two_routes) {
     hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, st, ctl, items[0], hist[0]);
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[0], &ctl->items[0],
                        &ctl->level_tiles[0], &ctl->items[1], ctl, 1);
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la0, x0, x1,
                        ctl);
+    level_prefix(&ctl->level_tiles[0], 1);
     PlanArgs pw{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
                 uniform, L.item_cap, ctl, cap_w, bits, 1};
     hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
@@ -1758,8 +1800,10 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     const int li = lev & 1;
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[li], &ctl->items[li],
                        &ctl->level_tiles[li], &ctl->items[li ^ 1], ctl, -1);
-    LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li], hist[li], cursor, wt0, wt1,
-                 bits, lev, -1};
+    // levels >= 1 split many buckets at once (at least one per set and top
+    // digit), so their atomics spread over many counters: atomic mode
+    LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li], hist[li], nullptr, cursor,
+                 wt0, wt1, bits, lev, -1};
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
     PlanArgs pl{items[li ^ 1], &ctl->items[li ^ 1], hist[li ^ 1], L.item_cap, batches,
                 L.batch_cap, uniform, L.item_cap, ctl, cap_u, bits, g0};
