@@ -963,13 +963,14 @@ __device__ __forceinline__ uint64_t key_hash(u128 k) {
   return ((uint64_t)k ^ ((uint64_t)(k >> 64) * 0xC2B2AE3D27D4EB4Full)) * 0x9E3779B97F4A7C15ull;
 }
 
-// LDS of the bucket sort.  Buffer 0 (key0/cnt0) is where every finished piece
-// of the sorted distinct keys lands; the table region is reused for buffer 1
-// and, at the end, for the expanded keys.
-// Counts of distinct keys: 16 bits suffice for unweighted batches (at most CAP
-// keys); summed record weights (W) take 32.
+// LDS of the bucket sort for keys of any width.  Buffer 0 (key0/cnt0) holds the
+// staged keys while duplicates are merged, then receives every finished piece of
+// the sorted distinct keys; the table region is reused for buffer 1.  Counts of
+// distinct keys: 16 bits suffice for unweighted batches (at most CAP keys);
+// summed record weights (W) take 32.
 template <typename K, bool W, int V>
 struct LocalLds {
+  using Key = K;
   using Cfg = LocalCfg<K, W, V>;
   using CT = typename std::conditional<W, uint32_t, uint16_t>::type;
   static constexpr int NT = Cfg::NT, NW = NT / 64, CAP = Cfg::CAP;
@@ -990,26 +991,63 @@ struct LocalLds {
   uint32_t wsum[NW + 1];
   __device__ uint32_t *own() { return reinterpret_cast<uint32_t *>(t); }
   __device__ uint32_t *tcnt() { return reinterpret_cast<uint32_t *>(t) + SLOTS; }
+  __device__ K *k0() { return key0; }
+  __device__ CT *c0() { return cnt0; }
   __device__ K *key1() { return reinterpret_cast<K *>(t); }
   __device__ CT *cnt1() { return reinterpret_cast<CT *>(t + (size_t)CAP * sizeof(K)); }
   __device__ K *keys_of(uint32_t b) { return b ? key1() : key0; }
   __device__ CT *cnts_of(uint32_t b) { return b ? cnt1() : cnt0; }
 };
 
+// LDS of the 64-bit bucket sort: one region is the hash table (a key and a
+// count per slot) while duplicates are merged, and the two piece buffers
+// afterwards; it is cleared before every batch.  An all-ones key marks an empty
+// slot: it is never a key (for k <= 31 the all-T (k+1)-mer is not canonical, and
+// k-mer keys use at most 62 bits).
+template <bool W, int V>
+struct SlotLds {
+  using Key = uint64_t;
+  using Cfg = LocalCfg<uint64_t, W, V>;
+  using CT = typename std::conditional<W, uint32_t, uint16_t>::type;
+  static constexpr int NT = Cfg::NT, NW = NT / 64, CAP = Cfg::CAP;
+  static constexpr size_t BUF = (size_t)CAP * (sizeof(Key) + sizeof(CT));
+  static constexpr int SLOTS = (int)(2 * BUF / 12);
+  alignas(16) unsigned char r[2 * BUF];
+  uint16_t ulist[CAP];
+  uint32_t hist[NW][256];
+  uint64_t large[2][CAP / 64 + 1];
+  uint64_t mid[CAP / (Cfg::SMALL + 1) + 1];
+  uint32_t nlarge[2], nmid, nuniq, dirty;
+  Key wor[NW];
+  Key wand[NW];
+  uint32_t wsum[NW + 1];
+  __device__ unsigned long long *tkey() { return reinterpret_cast<unsigned long long *>(r); }
+  __device__ uint32_t *tcnt() { return reinterpret_cast<uint32_t *>(r + (size_t)SLOTS * 8); }
+  __device__ Key *k0() { return reinterpret_cast<Key *>(r); }
+  __device__ CT *c0() { return reinterpret_cast<CT *>(r + (size_t)CAP * sizeof(Key)); }
+  __device__ Key *key1() { return reinterpret_cast<Key *>(r + BUF); }
+  __device__ CT *cnt1() { return reinterpret_cast<CT *>(r + BUF + (size_t)CAP * sizeof(Key)); }
+  __device__ Key *keys_of(uint32_t b) { return b ? key1() : k0(); }
+  __device__ CT *cnts_of(uint32_t b) { return b ? cnt1() : c0(); }
+};
+
 // Finish or enqueue one segment [start, start+c) of distinct keys in buffer `buf`
 // whose keys agree above `shift`.  Called by one lane.
-template <typename K, bool W, int V>
-__device__ __forceinline__ void classify_segment(LocalLds<K, W, V> &s, uint32_t start,
-                                                 uint32_t c, int shift, uint32_t buf, int nxt) {
-  using CT = typename LocalLds<K, W, V>::CT;
-  constexpr int SMALL = LocalCfg<K, W, V>::SMALL;
+template <typename S>
+__device__ __forceinline__ void classify_segment(S &s, uint32_t start, uint32_t c, int shift,
+                                                 uint32_t buf, int nxt) {
+  using K = typename S::Key;
+  using CT = typename S::CT;
+  constexpr int SMALL = S::Cfg::SMALL;
   if (c == 0) return;
   K *kb = s.keys_of(buf);
   CT *cb = s.cnts_of(buf);
+  K *k0 = s.k0();
+  CT *c0 = s.c0();
   if (c == 1) {
     if (buf) {
-      s.key0[start] = kb[start];
-      s.cnt0[start] = cb[start];
+      k0[start] = kb[start];
+      c0[start] = cb[start];
     }
     return;
   }
@@ -1018,16 +1056,16 @@ __device__ __forceinline__ void classify_segment(LocalLds<K, W, V> &s, uint32_t 
     const K x = kb[start], y = kb[start + 1];
     const CT cx = cb[start], cy = cb[start + 1];
     const bool sw = y < x;
-    s.key0[start] = sw ? y : x;
-    s.key0[start + 1] = sw ? x : y;
-    s.cnt0[start] = sw ? cy : cx;
-    s.cnt0[start + 1] = sw ? cx : cy;
+    k0[start] = sw ? y : x;
+    k0[start + 1] = sw ? x : y;
+    c0[start] = sw ? cy : cx;
+    c0[start + 1] = sw ? cx : cy;
   } else if (c <= 4) {
-    network_segment<4, K, CT>(kb, cb, s.key0, s.cnt0, start, c);
+    network_segment<4, K, CT>(kb, cb, k0, c0, start, c);
   } else if (c <= 8) {
-    network_segment<8, K, CT>(kb, cb, s.key0, s.cnt0, start, c);
+    network_segment<8, K, CT>(kb, cb, k0, c0, start, c);
   } else if (c <= (uint32_t)SMALL) {
-    network_segment<SMALL, K, CT>(kb, cb, s.key0, s.cnt0, start, c);
+    network_segment<SMALL, K, CT>(kb, cb, k0, c0, start, c);
   } else if (c <= 64) {
     s.mid[atomicAdd(&s.nmid, 1u)] = seg_pack(start, c, shift, buf);
   } else {
@@ -1035,18 +1073,6 @@ __device__ __forceinline__ void classify_segment(LocalLds<K, W, V> &s, uint32_t 
   }
 }
 
-// Sort a batch of up to CAP keys (consecutive small buckets) in LDS:
-//  1. stage the keys (prefetched into registers during the previous batch) and
-//     find the bits in which they differ (OR ^ AND over all keys);
-//  2. insert each key into an LDS hash table keyed by the index of its first
-//     occurrence (whose staged key is compared), counting duplicates;
-//  3. read the distinct keys and counts out of the table into registers and
-//     partition them by the 8 bits below the highest differing bit (whole
-//     workgroup) into their final buffer, then finish each piece: up to SMALL
-//     keys by one lane's sorting network, up to 64 by one wave ranking each key
-//     against the others, larger ones by a wave partition on their next 8 bits;
-//  4. write the sorted distinct keys and their counts over the batch's first
-//     positions and mark those positions in the bitmap.
 // Bits [off, off + nu) of the bitmap set, the rest of [off, off + m) left
 // clear (the bitmap starts zeroed).  Words wholly inside the range belong to
 // this batch alone and are stored; the two boundary words are or-ed.
@@ -1068,6 +1094,228 @@ __device__ __forceinline__ void mark_positions(uint32_t *bits, uint64_t off, uin
   }
 }
 
+// After duplicates are merged: the batch's nu distinct keys and counts are in
+// registers (uk, uc: key u = tid + j NT), hb is the highest bit in which the
+// batch's keys differ.  Partition them by a digit of about log2(nu) bits just
+// below hb into buffer 0, sort every bucket of up to 64 keys by ranking each key
+// against the others, refine the rare larger pieces, then write the sorted
+// distinct keys over the batch's first positions of b0, their counts (halved for
+// weighted records) to the same positions of b1, and mark those positions in the
+// bitmap.  Ends with a barrier.  The caller must have passed a barrier after its
+// last read of the LDS the buffers overwrite.
+template <typename S, bool W, int UPT>
+__device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[UPT],
+                                             const uint32_t (&uc)[UPT], uint32_t nu, int hb,
+                                             int dw_bias, const Batch &bt,
+                                             typename S::Key *b0, typename S::Key *b1,
+                                             uint32_t *bits) {
+  using K = typename S::Key;
+  using CT = typename S::CT;
+  constexpr int NT = S::NT, NW = S::NW;
+  static_assert(NW * 256 == 4 * NT, "the first partition's bins: 4 per thread");
+  static_assert(4 * NT <= S::CAP, "bucket starts are kept in the distinct-key list");
+  constexpr int MAXDW = NW >= 8 ? 11 : 10;  // log2 of the NW * 256 bins
+  const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+  K *key0 = s.k0();
+  CT *cnt0 = s.c0();
+  // digit width: about one distinct key per bucket (shifted by the tuning's
+  // bias), at most MAXDW bits, taken just below hb
+  int dw = (nu <= 256 ? 8 : bit_length((uint64_t)(nu - 1))) + dw_bias;
+  dw = dw < 1 ? 1 : dw > MAXDW ? MAXDW : dw;
+  dw = dw > hb ? hb : dw;
+  const int dshift = hb - dw;
+  uint32_t *H = &s.hist[0][0];  // NW * 256 bins, zeroed by the caller
+  uint32_t ud[UPT];
+#pragma unroll
+  for (int j = 0; j < UPT; ++j) {
+    ud[j] = 0;
+    if (tid + (uint32_t)j * NT < nu) {
+      ud[j] = dw > 0 ? (uint32_t)shr<K>(uk[j], dshift) & ((1u << dw) - 1u) : 0u;
+      atomicAdd(&H[ud[j]], 1u);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) s.nuniq = 0;  // every thread holds nu; ready for the next batch
+  // thread t owns bins 4t .. 4t+3
+  uint32_t c4[4], st4[4], sum4 = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    c4[q] = H[4 * tid + q];
+    sum4 += c4[q];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan<NT>(sum4, s.wsum, &tot);
+  uint16_t *bstart = s.ulist;  // the list is read out: it now keeps the bucket starts
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    st4[q] = run;
+    H[4 * tid + q] = run;
+    bstart[4 * tid + q] = (uint16_t)run;
+    run += c4[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < UPT; ++j)
+    if (tid + (uint32_t)j * NT < nu) {
+      const uint32_t q = atomicAdd(&H[ud[j]], 1u);
+      key0[q] = uk[j];
+      cnt0[q] = (CT)uc[j];
+    }
+  __syncthreads();
+  // buckets of up to 64 keys: every distinct key counts the smaller keys of
+  // its bucket, then all of them move to their final places at once (the
+  // reads finish before the barrier, so the moves can be in place)
+  constexpr uint32_t NOPOS = 0xffffffffu;
+  uint32_t fin[UPT];
+#pragma unroll
+  for (int j = 0; j < UPT; ++j) {
+    fin[j] = NOPOS;
+    if (tid + (uint32_t)j * NT < nu) {
+      const uint32_t b = bstart[ud[j]], e = H[ud[j]];
+      if (e - b <= 64u) {
+        uint32_t r = 0;
+        for (uint32_t i = b; i < e; ++i) r += key0[i] < uk[j] ? 1u : 0u;
+        fin[j] = b + r;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < UPT; ++j)
+    if (fin[j] != NOPOS) {
+      key0[fin[j]] = uk[j];
+      cnt0[fin[j]] = (CT)uc[j];
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (c4[q] > 64u) classify_segment(s, st4[q], c4[q], dshift, 0u, 0);
+  __syncthreads();
+  // pieces left over (usually none): refined until every piece is finished
+  int cur = 0;
+  while (s.nmid != 0 || s.nlarge[cur] != 0) {
+    // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
+    for (uint32_t i = w; i < s.nmid; i += NW) {
+      const uint64_t d = s.mid[i];
+      const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
+      const K *kb = s.keys_of(buf);
+      const CT *cb = s.cnts_of(buf);
+      const uint32_t me = lane;
+      const K x = me < c ? kb[st + me] : all_ones<K>();
+      const uint32_t xc = me < c ? cb[st + me] : 0u;
+      uint32_t rank = 0;
+      for (uint32_t j = 0; j < c; ++j) rank += kb[st + j] < x ? 1u : 0u;
+      // c <= 64, so this runs once per piece: when the piece is already in
+      // buffer 0 the wave's reads above precede its writes below (LDS
+      // operations of one wave complete in order)
+      if (me < c) {
+        key0[st + rank] = x;
+        cnt0[st + rank] = (CT)xc;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s.nmid = 0;
+    const uint32_t nl = s.nlarge[cur];
+    __syncthreads();
+    if (nl == 0) break;
+    // larger pieces: one wave each, partitioned by the 8 bits below their
+    // highest differing bit into the other buffer
+    for (uint32_t i = w; i < nl; i += NW) {
+      const uint64_t d = s.large[cur][i];
+      const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
+      const K *ik = s.keys_of(buf);
+      const CT *ic = s.cnts_of(buf);
+      K *ok = s.keys_of(buf ^ 1u);
+      CT *oc = s.cnts_of(buf ^ 1u);
+      if (buf == 0 && lane == 0) s.dirty = 1;  // buffer 1 overwrites the hash table
+      uint32_t *h = s.hist[w];
+      K dd = 0;
+      const K kk = ik[st];
+      for (uint32_t e = lane; e < c; e += 64) dd |= ik[st + e] ^ kk;
+      const int shift = bit_length(wave_or_key(dd));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[lane + 64 * q] = 0;
+      for (uint32_t e = lane; e < c; e += 64) atomicAdd(&h[seg_digit(ik[st + e], shift)], 1u);
+      uint32_t cnt[4], pre[4], sum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cnt[q] = h[4 * lane + q];
+        pre[q] = sum;
+        sum += cnt[q];
+      }
+      const uint32_t base = st + wave_inclusive_scan(sum) - sum;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[4 * lane + q] = base + pre[q];
+      for (uint32_t e = lane; e < c; e += 64) {
+        const K key = ik[st + e];
+        const uint32_t q = atomicAdd(&h[seg_digit(key, shift)], 1u);
+        ok[q] = key;
+        oc[q] = ic[st + e];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        classify_segment(s, base + pre[q], cnt[q], shift - 8, buf ^ 1u, cur ^ 1);
+    }
+    __syncthreads();
+    if (tid == 0) s.nlarge[cur] = 0;
+    cur ^= 1;
+    __syncthreads();
+  }
+  // the batch's distinct keys, sorted, replace its first positions in buffer 0,
+  // their counts go to the same positions of buffer 1, and the bitmap marks
+  // those positions
+  for (uint32_t u = tid; u < nu; u += NT) {
+    b0[bt.off + u] = key0[u];
+    b1[bt.off + u] = (K)((uint32_t)cnt0[u] >> (W ? 1 : 0));
+  }
+  mark_positions(bits, bt.off, bt.size, nu);
+  __syncthreads();
+}
+
+// Keys (and weights) of a batch into registers: key e = tid + j NT.
+template <typename K, bool W, int NT, int LPT>
+__device__ __forceinline__ void load_batch(const Batch &b, const K *b0, const K *b1,
+                                           const uint32_t *w0, const uint32_t *w1,
+                                           K (&pre)[LPT], uint32_t (&prew)[W ? LPT : 1]) {
+  const K *src = b.src ? b1 : b0;
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+    const uint32_t e = threadIdx.x + (uint32_t)j * NT;
+    pre[j] = e < b.size ? src[b.off + e] : K(0);
+  }
+  if (W) {
+    const uint32_t *srcw = b.src ? w1 : w0;
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      const uint32_t e = threadIdx.x + (uint32_t)j * NT;
+      prew[j] = e < b.size ? srcw[b.off + e] : 0u;
+    }
+  }
+}
+
+// Claimed slots of a wave appended to the distinct-key list with one atomic.
+template <typename S, int LPT>
+__device__ __forceinline__ void record_claims(S &s, uint32_t claimed, uint32_t ncl,
+                                              const uint32_t (&hs)[LPT]) {
+  const uint32_t incl = wave_inclusive_scan(ncl);
+  const uint32_t wtot = __shfl(incl, 63, 64);
+  uint32_t base = 0;
+  if (lane_id() == 0 && wtot) base = atomicAdd(&s.nuniq, wtot);
+  base = __shfl(base, 0, 64) + incl - ncl;
+#pragma unroll
+  for (int j = 0; j < LPT; ++j)
+    if (claimed & (1u << j)) s.ulist[base++] = (uint16_t)hs[j];
+}
+
+// Sort a batch of up to CAP keys (consecutive small buckets) in LDS:
+//  1. the batch's keys (loaded into registers while the previous batch was
+//     sorted) and the bits in which they differ (OR ^ AND over all keys);
+//  2. each key inserted into an LDS hash table, counting duplicates (summing
+//     weights for weighted records);
+//  3. the distinct keys and counts read out of the table into registers and
+//     sorted by finish_batch, which writes them out.
+// k_local_sort keys its table by the index of each key's first occurrence in
+// the staged batch (so 128-bit keys need no 128-bit CAS); k_local_sort64 keeps
+// 64-bit keys in the table slots themselves (no staging, one 64-bit CAS per key).
 // W: weighted records (node table from edge endpoints): the weights, stored
 // beside the keys in w0 / w1, are summed per distinct key instead of counting
 // occurrences, and the sum is halved on output (each k-mer occurrence is seen
@@ -1076,40 +1324,18 @@ template <typename K, bool W, int V>
 __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     const Batch *batches, const uint64_t *n_batches_p, K *b0, K *b1, const uint32_t *w0,
     const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate, int dw_bias) {
-  using Cfg = LocalCfg<K, W, V>;
-  using CT = typename LocalLds<K, W, V>::CT;
-  constexpr int NT = Cfg::NT, NW = NT / 64, SLOTS = Cfg::SLOTS;
+  using S = LocalLds<K, W, V>;
+  constexpr int NT = S::NT, NW = S::NW, SLOTS = S::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
-  constexpr int LPT = (Cfg::CAP + NT - 1) / NT;  // keys per thread
-  static_assert(NW * 256 == 4 * NT, "the first partition's bins: 4 per thread");
-  static_assert(4 * NT <= Cfg::CAP, "bucket starts are kept in the distinct-key list");
-  constexpr int MAXDW = NW >= 8 ? 11 : 10;  // log2 of the NW * 256 bins
-  __shared__ LocalLds<K, W, V> s;
+  constexpr int LPT = (S::CAP + NT - 1) / NT;  // keys per thread
+  __shared__ S s;
   if (ctl->status || gated_off(ctl, gate)) return;
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const uint64_t n_batches = *n_batches_p;
   const uint64_t G = gridDim.x;
   uint32_t *own = s.own(), *tcnt = s.tcnt();
-  // software pipeline: the keys of the next batch are loaded into registers
-  // while this one is processed in LDS (descriptors are read two batches ahead)
   K pre[LPT];
   uint32_t prew[W ? LPT : 1];
-  auto prefetch = [&](const Batch &b) {
-    const K *src = b.src ? b1 : b0;
-#pragma unroll
-    for (int j = 0; j < LPT; ++j) {
-      const uint32_t e = tid + (uint32_t)j * NT;
-      pre[j] = e < b.size ? src[b.off + e] : K(0);
-    }
-    if (W) {
-      const uint32_t *srcw = b.src ? w1 : w0;
-#pragma unroll
-      for (int j = 0; j < LPT; ++j) {
-        const uint32_t e = tid + (uint32_t)j * NT;
-        prew[j] = e < b.size ? srcw[b.off + e] : 0u;
-      }
-    }
-  };
   if (tid == 0) {
     s.dirty = 1;  // the table starts uninitialised
     s.nuniq = s.nmid = 0;
@@ -1118,7 +1344,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
   __syncthreads();
   const Batch none = {0, 0, 0};
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
-  prefetch(nxt);
+  load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
   Batch nxt2 = blockIdx.x + G < n_batches ? batches[blockIdx.x + G] : none;
   for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
     const Batch bt = nxt;
@@ -1151,11 +1377,11 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     for (uint32_t q = tid; q < (uint32_t)(NW * 256); q += NT) s.hist[0][q] = 0;
     __syncthreads();
     if (tid == 0) s.dirty = 0;
-    // 2. count duplicates in an LDS hash table keyed by the first occurrence
+    // 2. count duplicates in an LDS hash table keyed by the first occurrence:
+    //    first probe of every key of this thread at once (independent LDS
+    //    atomics in flight), then the keys that own the probed slots (again all
+    //    at once), then linear probing for the few that collided
     {
-      // first probe of every key of this thread at once (independent LDS
-      // atomics in flight), then the keys that own the probed slots (again all
-      // at once), then linear probing for the few that collided
       uint32_t hs[LPT], os[LPT];
 #pragma unroll
       for (int j = 0; j < LPT; ++j) {
@@ -1191,22 +1417,14 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
           atomicAdd(&tcnt[h], W ? prew[j] : 1u);
         }
       }
-      // record the claimed slots: one LDS atomic per wave
-      const uint32_t incl = wave_inclusive_scan(ncl);
-      const uint32_t wtot = __shfl(incl, 63, 64);
-      uint32_t base = 0;
-      if (lane == 0 && wtot) base = atomicAdd(&s.nuniq, wtot);
-      base = __shfl(base, 0, 64) + incl - ncl;
-#pragma unroll
-      for (int j = 0; j < LPT; ++j)
-        if (claimed & (1u << j)) s.ulist[base++] = (uint16_t)hs[j];
+      record_claims(s, claimed, ncl, hs);
     }
     __syncthreads();
     // the next batch's keys load while this one is sorted (descriptors are read
     // two batches ahead)
     nxt = nxt2;
     nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
-    if (bi + G < n_batches) prefetch(nxt);
+    if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
     K kall_or = 0, kall_and = all_ones<K>();
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
@@ -1214,172 +1432,148 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
       kall_and &= s.wand[i];
     }
     const int hb = bit_length(kall_or ^ kall_and);
-    // 3. distinct keys (read from the table into registers through the list of
-    //    claimed slots) partitioned by the 8 bits below hb straight into buffer 0
+    // 3. distinct keys read from the table into registers through the list of
+    //    claimed slots (which are reset for the next batch)
     const uint32_t nu = s.nuniq;
-    // digit width: about one distinct key per bucket (shifted by the tuning's
-    // bias), at most MAXDW bits, taken just below hb
-    int dw = (nu <= 256 ? 8 : bit_length((uint64_t)(nu - 1))) + dw_bias;
-    dw = dw < 1 ? 1 : dw > MAXDW ? MAXDW : dw;
-    dw = dw > hb ? hb : dw;
-    const int dshift = hb - dw;
-    uint32_t *H = &s.hist[0][0];  // NW * 256 bins
-    constexpr int UPT = (Cfg::CAP + NT - 1) / NT;
-    K uk[UPT];
-    uint32_t uc[UPT], ud[UPT];
+    K uk[LPT];
+    uint32_t uc[LPT];
 #pragma unroll
-    for (int j = 0; j < UPT; ++j) {
+    for (int j = 0; j < LPT; ++j) {
       const uint32_t u = tid + (uint32_t)j * NT;
       uc[j] = 0;
-      ud[j] = 0;
       uk[j] = K(0);
       if (u < nu) {
         const uint32_t q = s.ulist[u];
         uk[j] = s.key0[own[q]];
         uc[j] = tcnt[q];
-        ud[j] = dw > 0 ? (uint32_t)shr<K>(uk[j], dshift) & ((1u << dw) - 1u) : 0u;
-        atomicAdd(&H[ud[j]], 1u);
-        own[q] = EMPTY;  // leave the table clean for the next batch
+        own[q] = EMPTY;
         tcnt[q] = 0;
       }
     }
-    __syncthreads();
-    if (tid == 0) s.nuniq = 0;  // every thread holds nu; ready for the next batch
-    // thread t owns bins 4t .. 4t+3
-    uint32_t c4[4], st4[4], sum4 = 0;
+    finish_batch<S, W, LPT>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
+  }
+}
+
+template <bool W, int V>
+__global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) void k_local_sort64(
+    const Batch *batches, const uint64_t *n_batches_p, uint64_t *b0, uint64_t *b1,
+    const uint32_t *w0, const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate,
+    int dw_bias) {
+  using S = SlotLds<W, V>;
+  using K = uint64_t;
+  constexpr int NT = S::NT, NW = S::NW, SLOTS = S::SLOTS;
+  constexpr unsigned long long EMPTY = ~0ull;
+  constexpr int LPT = (S::CAP + NT - 1) / NT;  // keys per thread
+  __shared__ S s;
+  if (ctl->status || gated_off(ctl, gate)) return;
+  const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+  const uint64_t n_batches = *n_batches_p;
+  const uint64_t G = gridDim.x;
+  unsigned long long *tkey = s.tkey();
+  uint32_t *tcnt = s.tcnt();
+  K pre[LPT];
+  uint32_t prew[W ? LPT : 1];
+  if (tid == 0) {
+    s.nuniq = s.nmid = 0;
+    s.nlarge[0] = s.nlarge[1] = 0;
+  }
+  const Batch none = {0, 0, 0};
+  Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
+  load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
+  Batch nxt2 = blockIdx.x + G < n_batches ? batches[blockIdx.x + G] : none;
+  for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
+    const Batch bt = nxt;
+    const uint32_t m = bt.size;
+    // 1. the bits in which the batch's keys differ (OR ^ AND); the region was
+    //    last read before the previous batch's final barrier, so it is cleared
+    //    here: empty key slots, zero counts
+    K kor = 0, kand = all_ones<K>();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      c4[q] = H[4 * tid + q];
-      sum4 += c4[q];
-    }
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan<NT>(sum4, s.wsum, &tot);
-    uint16_t *bstart = s.ulist;  // the list is read out: it now keeps the bucket starts
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      st4[q] = run;
-      H[4 * tid + q] = run;
-      bstart[4 * tid + q] = (uint16_t)run;
-      run += c4[q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < UPT; ++j)
-      if (tid + (uint32_t)j * NT < nu) {
-        const uint32_t q = atomicAdd(&H[ud[j]], 1u);
-        s.key0[q] = uk[j];
-        s.cnt0[q] = (CT)uc[j];
+    for (int j = 0; j < LPT; ++j)
+      if (tid + (uint32_t)j * NT < m) {
+        kor |= pre[j];
+        kand &= pre[j];
       }
+    kor = wave_or_key(kor);
+    kand = wave_and_key(kand);
+    if (lane == 0) {
+      s.wor[w] = kor;
+      s.wand[w] = kand;
+    }
+    {
+      uint4 *r4 = reinterpret_cast<uint4 *>(s.r);
+      constexpr uint32_t nkey4 = (uint32_t)SLOTS * 8 / 16, ncnt4 = (uint32_t)SLOTS * 4 / 16;
+      const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u), zeros = make_uint4(0u, 0u, 0u, 0u);
+      for (uint32_t q = tid; q < nkey4; q += NT) r4[q] = ones;
+      for (uint32_t q = tid; q < ncnt4; q += NT) r4[nkey4 + q] = zeros;
+    }
+    for (uint32_t q = tid; q < (uint32_t)(NW * 256); q += NT) s.hist[0][q] = 0;
     __syncthreads();
-    // buckets of up to 64 keys: every distinct key counts the smaller keys of
-    // its bucket, then all of them move to their final places at once (the
-    // reads finish before the barrier, so the moves can be in place)
-    constexpr uint32_t NOPOS = 0xffffffffu;
-    uint32_t fin[UPT];
+    // 2. count duplicates in an LDS hash table holding the keys: first probe of
+    //    every key of this thread at once, then linear probing for the few
+    //    that collided
+    {
+      uint32_t hs[LPT];
+      unsigned long long os[LPT];
 #pragma unroll
-    for (int j = 0; j < UPT; ++j) {
-      fin[j] = NOPOS;
-      if (tid + (uint32_t)j * NT < nu) {
-        const uint32_t b = bstart[ud[j]], e = H[ud[j]];
-        if (e - b <= 64u) {
-          uint32_t r = 0;
-          for (uint32_t i = b; i < e; ++i) r += s.key0[i] < uk[j] ? 1u : 0u;
-          fin[j] = b + r;
+      for (int j = 0; j < LPT; ++j) {
+        const uint32_t e = tid + (uint32_t)j * NT;
+        hs[j] = 0;
+        os[j] = EMPTY;
+        if (e < m) {
+          hs[j] = (uint32_t)(((key_hash(pre[j]) >> 32) * (uint64_t)SLOTS) >> 32);
+          os[j] = atomicCAS(&tkey[hs[j]], EMPTY, (unsigned long long)pre[j]);
         }
       }
-    }
-    __syncthreads();
+      uint32_t claimed = 0, ncl = 0;  // bit j: this thread's key j claimed slot hs[j]
 #pragma unroll
-    for (int j = 0; j < UPT; ++j)
-      if (fin[j] != NOPOS) {
-        s.key0[fin[j]] = uk[j];
-        s.cnt0[fin[j]] = (CT)uc[j];
-      }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (c4[q] > 64u) classify_segment<K, W, V>(s, st4[q], c4[q], dshift, 0u, 0);
-    __syncthreads();
-    // pieces left over (usually none): refined until every piece is finished
-    int cur = 0;
-    while (s.nmid != 0 || s.nlarge[cur] != 0) {
-      // pieces of SMALL+1..64 keys (or with no bits left): lane ranks its keys
-      for (uint32_t i = w; i < s.nmid; i += NW) {
-        const uint64_t d = s.mid[i];
-        const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
-        const K *kb = s.keys_of(buf);
-        const CT *cb = s.cnts_of(buf);
-        {
-          const uint32_t me = lane;
-          const K x = me < c ? kb[st + me] : all_ones<K>();
-          const uint32_t xc = me < c ? cb[st + me] : 0u;
-          uint32_t rank = 0;
-          for (uint32_t j = 0; j < c; ++j) rank += kb[st + j] < x ? 1u : 0u;
-          // c <= 64, so this loop runs once: when the piece is already in
-          // buffer 0 the wave's reads above precede its writes below (LDS
-          // operations of one wave complete in order)
-          if (me < c) {
-            s.key0[st + rank] = x;
-            s.cnt0[st + rank] = (CT)xc;
+      for (int j = 0; j < LPT; ++j) {
+        const uint32_t e = tid + (uint32_t)j * NT;
+        if (e < m) {
+          const unsigned long long key = pre[j];
+          uint32_t h = hs[j];
+          unsigned long long o = os[j];
+          while (o != EMPTY && o != key) {
+            h = h + 1 == (uint32_t)SLOTS ? 0u : h + 1;
+            o = atomicCAS(&tkey[h], EMPTY, key);
           }
+          hs[j] = h;
+          if (o == EMPTY) {
+            claimed |= 1u << j;
+            ++ncl;
+          }
+          atomicAdd(&tcnt[h], W ? prew[j] : 1u);
         }
       }
-      __syncthreads();
-      if (tid == 0) s.nmid = 0;
-      const uint32_t nl = s.nlarge[cur];
-      __syncthreads();
-      if (nl == 0) break;
-      // larger pieces: one wave each, partitioned by the 8 bits below their
-      // highest differing bit into the other buffer
-      for (uint32_t i = w; i < nl; i += NW) {
-        const uint64_t d = s.large[cur][i];
-        const uint32_t st = seg_start(d), c = seg_size(d), buf = seg_buf(d);
-        const K *ik = s.keys_of(buf);
-        const CT *ic = s.cnts_of(buf);
-        K *ok = s.keys_of(buf ^ 1u);
-        CT *oc = s.cnts_of(buf ^ 1u);
-        if (buf == 0 && lane == 0) s.dirty = 1;  // buffer 1 overwrites the hash table
-        uint32_t *h = s.hist[w];
-        K dd = 0;
-        const K kk = ik[st];
-        for (uint32_t e = lane; e < c; e += 64) dd |= ik[st + e] ^ kk;
-        const int shift = bit_length(wave_or_key(dd));
-#pragma unroll
-        for (int q = 0; q < 4; ++q) h[lane + 64 * q] = 0;
-        for (uint32_t e = lane; e < c; e += 64) atomicAdd(&h[seg_digit(ik[st + e], shift)], 1u);
-        uint32_t cnt[4], pre[4], sum = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          cnt[q] = h[4 * lane + q];
-          pre[q] = sum;
-          sum += cnt[q];
-        }
-        const uint32_t base = st + wave_inclusive_scan(sum) - sum;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) h[4 * lane + q] = base + pre[q];
-        for (uint32_t e = lane; e < c; e += 64) {
-          const K key = ik[st + e];
-          const uint32_t q = atomicAdd(&h[seg_digit(key, shift)], 1u);
-          ok[q] = key;
-          oc[q] = ic[st + e];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          classify_segment<K, W, V>(s, base + pre[q], cnt[q], shift - 8, buf ^ 1u, cur ^ 1);
-      }
-      __syncthreads();
-      if (tid == 0) s.nlarge[cur] = 0;
-      cur ^= 1;
-      __syncthreads();
+      record_claims(s, claimed, ncl, hs);
     }
-    // 4. the batch's distinct keys, sorted, replace its first positions in
-    //    buffer 0, their counts go to the same positions of buffer 1, and the
-    //    bitmap marks those positions
-    for (uint32_t u = tid; u < nu; u += NT) {
-      b0[bt.off + u] = s.key0[u];
-      b1[bt.off + u] = (K)((uint32_t)s.cnt0[u] >> (W ? 1 : 0));
-    }
-    mark_positions(bits, bt.off, m, nu);
     __syncthreads();
+    nxt = nxt2;
+    nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
+    if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
+    K kall_or = 0, kall_and = all_ones<K>();
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      kall_or |= s.wor[i];
+      kall_and &= s.wand[i];
+    }
+    const int hb = bit_length(kall_or ^ kall_and);
+    // 3. distinct keys and counts read out through the list of claimed slots
+    const uint32_t nu = s.nuniq;
+    K uk[LPT];
+    uint32_t uc[LPT];
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      const uint32_t u = tid + (uint32_t)j * NT;
+      uc[j] = 0;
+      uk[j] = K(0);
+      if (u < nu) {
+        const uint32_t q = s.ulist[u];
+        uk[j] = (K)tkey[q];
+        uc[j] = tcnt[q];
+      }
+    }
+    finish_batch<S, W, LPT>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
   }
 }
 
@@ -1670,6 +1864,23 @@ static inline void stage(int idx, hipStream_t st) {
   if (g_stage_events) (void)hipEventRecord(g_stage_events[idx], st);
 }
 
+// The LDS bucket sort: 64-bit keys live in the hash table's slots, 128-bit keys
+// are hashed by the index of their first occurrence.  One workgroup (512
+// threads) or two (256 threads) per CU, persistent over the batch list.
+template <typename K, bool W, int V>
+static void launch_local_sort(unsigned grid, hipStream_t st, const Batch *batches,
+                              const uint64_t *n_batches, K *x0, K *x1, const uint32_t *wt0,
+                              const uint32_t *wt1, uint32_t *bits, const Ctl *ctl, int gate,
+                              int bias) {
+  if constexpr (sizeof(K) == 8)
+    hipLaunchKernelGGL((k_local_sort64<W, V>), dim3(grid), dim3(LocalCfg<K, W, V>::NT), 0, st,
+                       batches, n_batches, reinterpret_cast<uint64_t *>(x0),
+                       reinterpret_cast<uint64_t *>(x1), wt0, wt1, bits, ctl, gate, bias);
+  else
+    hipLaunchKernelGGL((k_local_sort<K, W, V>), dim3(grid), dim3(LocalCfg<K, W, V>::NT), 0, st,
+                       batches, n_batches, x0, x1, wt0, wt1, bits, ctl, gate, bias);
+}
+
 static inline unsigned grid_for(uint64_t n, uint64_t per, uint64_t cap) {
   uint64_t g = (n + per - 1) / per;
   if (g < 1) g = 1;
@@ -1830,21 +2041,17 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                      st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
   const int bias = A.tuning.lds_digit_bias;
   if (lv == 0) {
-    hipLaunchKernelGGL((k_local_sort<K, false, 0>), dim3(grid_for(L.batch_cap, 1, 256)),
-                       dim3(LocalCfg<K, false, 0>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
-                       wt0, wt1, runbits, ctl, g0, bias);
+    launch_local_sort<K, false, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, runbits,
+                                   ctl, g0, bias);
     if (two_routes)
-      hipLaunchKernelGGL((k_local_sort<K, true, 0>), dim3(grid_for(L.batch_cap, 1, 256)),
-                         dim3(LocalCfg<K, true, 0>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
-                         wt0, wt1, runbits, ctl, 1, bias);
+      launch_local_sort<K, true, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
+                                    runbits, ctl, 1, bias);
   } else {
-    hipLaunchKernelGGL((k_local_sort<K, false, 1>), dim3(grid_for(L.batch_cap, 1, 512)),
-                       dim3(LocalCfg<K, false, 1>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
-                       wt0, wt1, runbits, ctl, g0, bias);
+    launch_local_sort<K, false, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, runbits,
+                                   ctl, g0, bias);
     if (two_routes)
-      hipLaunchKernelGGL((k_local_sort<K, true, 1>), dim3(grid_for(L.batch_cap, 1, 512)),
-                         dim3(LocalCfg<K, true, 1>::NT), 0, st, batches, &ctl->n_batches, x0, x1,
-                         wt0, wt1, runbits, ctl, 1, bias);
+      launch_local_sort<K, true, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
+                                    runbits, ctl, 1, bias);
   }
   stage(ev + 6, st);
   hipLaunchKernelGGL(k_uniform_emit<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
