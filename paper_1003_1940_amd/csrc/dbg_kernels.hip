@@ -1474,9 +1474,12 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) void k_local_sort64
   K pre[LPT];
   uint32_t prew[W ? LPT : 1];
   if (tid == 0) {
+    s.dirty = 1;  // the region starts uninitialised
     s.nuniq = s.nmid = 0;
     s.nlarge[0] = s.nlarge[1] = 0;
   }
+  __syncthreads();
+  uint32_t prev_nu = 0;  // distinct keys of the previous batch, left in buffer 0
   const Batch none = {0, 0, 0};
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
   load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
@@ -1485,8 +1488,10 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) void k_local_sort64
     const Batch bt = nxt;
     const uint32_t m = bt.size;
     // 1. the bits in which the batch's keys differ (OR ^ AND); the region was
-    //    last read before the previous batch's final barrier, so it is cleared
-    //    here: empty key slots, zero counts
+    //    last read before the previous batch's final barrier, so it is made an
+    //    empty table again here: the readout reset the claimed slots, so only
+    //    the slots that buffer 0 overwrote need resetting, unless buffer 1 was
+    //    used too (then all of it)
     K kor = 0, kand = all_ones<K>();
 #pragma unroll
     for (int j = 0; j < LPT; ++j)
@@ -1500,15 +1505,22 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) void k_local_sort64
       s.wor[w] = kor;
       s.wand[w] = kand;
     }
-    {
+    if (s.dirty) {  // uniform: read after the previous batch's final barrier
       uint4 *r4 = reinterpret_cast<uint4 *>(s.r);
       constexpr uint32_t nkey4 = (uint32_t)SLOTS * 8 / 16, ncnt4 = (uint32_t)SLOTS * 4 / 16;
       const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u), zeros = make_uint4(0u, 0u, 0u, 0u);
       for (uint32_t q = tid; q < nkey4; q += NT) r4[q] = ones;
       for (uint32_t q = tid; q < ncnt4; q += NT) r4[nkey4 + q] = zeros;
+    } else {
+      // key0 = slots [0, nu), cnt0 = slots from CAP on (both inside the key part)
+      constexpr uint32_t cslot = (uint32_t)(S::CAP * sizeof(K) / 8);
+      const uint32_t ncs = (uint32_t)((prev_nu * sizeof(typename S::CT) + 7) / 8);
+      for (uint32_t q = tid; q < prev_nu; q += NT) tkey[q] = EMPTY;
+      for (uint32_t q = tid; q < ncs; q += NT) tkey[cslot + q] = EMPTY;
     }
     for (uint32_t q = tid; q < (uint32_t)(NW * 256); q += NT) s.hist[0][q] = 0;
     __syncthreads();
+    if (tid == 0) s.dirty = 0;
     // 2. count duplicates in an LDS hash table holding the keys: first probe of
     //    every key of this thread at once, then linear probing for the few
     //    that collided
@@ -1571,9 +1583,12 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) void k_local_sort64
         const uint32_t q = s.ulist[u];
         uk[j] = (K)tkey[q];
         uc[j] = tcnt[q];
+        tkey[q] = EMPTY;  // leave the table empty for the next batch
+        tcnt[q] = 0;
       }
     }
     finish_batch<S, W, LPT>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
+    prev_nu = nu;
   }
 }
 
