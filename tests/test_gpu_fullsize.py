@@ -32,7 +32,11 @@ def repeats_full():
     say("[gpu-fullsize] building on the GPU")
     g, got = gpu_graph(rs.bases, rs.offsets, 31)
     assert g.status == 0
-    return rs, g, got
+    yield rs, g, got
+    del g
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()  # later tests size their budgets from free HBM
 
 
 def test_fullsize_invariants(repeats_full):
