@@ -214,6 +214,30 @@ int dbg_set_tuning(const dbg_tuning_t *tuning);
 /* Copies the current tuning into *tuning (DBG_E_NULL if null). */
 int dbg_get_tuning(dbg_tuning_t *tuning);
 
+/* STEP-4 of Sec. 3: adjacency lists of a built graph.  Each distinct edge
+ * (u, v, o1, o2) has two ends, the u end on side o1 of node u and the v end on
+ * side o2 of node v ('+' = 0, '-' = 1); a self-loop gives its node two ends.  The
+ * lists group the ends by (node, side) -- nodes in node-table order, side '+'
+ * first -- and order each group by edge row, u end first.  Output as a CSR over
+ * the 2 n_nodes buckets b = 2 * node + side:
+ *   offsets   device, 2 n_nodes + 1 uint64_t: bucket b holds entries
+ *             offsets[b] .. offsets[b + 1] - 1;
+ *   inc_edge  device, 2 n_edges uint32_t: edge row of each entry;
+ *   inc_end   device, 2 n_edges bytes: 0 for the u end, 1 for the v end.
+ * Inputs are a build's tables (device): node_kmer (n_nodes keys, ascending),
+ * edge_u / edge_v / edge_orient (n_edges rows), key width as in dbg_build; the
+ * counts are the build's n_nodes / n_edges (read from its result record).
+ * result (device) receives status DBG_OK, or DBG_E_ARG when an edge endpoint is
+ * not in the node table (then the entries are not written).  Host errors:
+ * DBG_E_K, DBG_E_NULL, DBG_E_ARG (edges without nodes), DBG_E_OVERFLOW
+ * (n_nodes >= 2^31 or n_edges >= 2^32), DBG_E_WORKSPACE.  Enqueues on `stream`,
+ * never synchronises or allocates. */
+size_t dbg_adjacency_workspace_bytes(uint64_t n_nodes, uint64_t n_edges, int k);
+int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
+                  const void *edge_v, const uint8_t *edge_orient, uint64_t n_edges, int k,
+                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, dbg_result_t *result,
+                  void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Static description of a status code. */
 const char *dbg_strerror(int status);
 

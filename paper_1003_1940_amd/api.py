@@ -77,6 +77,10 @@ def load():
         lib.dbg_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         lib.dbg_get_tuning.restype = i32
         lib.dbg_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
+        lib.dbg_adjacency_workspace_bytes.restype = sz
+        lib.dbg_adjacency_workspace_bytes.argtypes = [u64, u64, i32]
+        lib.dbg_adjacency.restype = i32
+        lib.dbg_adjacency.argtypes = [vp, u64, vp, vp, vp, u64, i32, vp, vp, vp, vp, vp, sz, vp]
         lib.dbg_strerror.restype = ctypes.c_char_p
         lib.dbg_strerror.argtypes = [i32]
         _lib = lib
@@ -400,3 +404,51 @@ class CapturedBuild:
                   node_set_offsets=self.node_set_offsets, edge_set_offsets=self.edge_set_offsets)
         g.extra["flags"] = read_flags(self.result)
         return g
+
+
+@dataclass
+class Adjacency:
+    """STEP-4 adjacency lists as a CSR over buckets b = 2 * node + side: entries
+    offsets[b] .. offsets[b+1] of (edge row, end), end 0 = the u end."""
+    offsets: torch.Tensor    # int64, 2 n_nodes + 1
+    inc_edge: torch.Tensor   # int32 holding uint32 edge rows, 2 n_edges
+    inc_end: torch.Tensor    # uint8, 2 n_edges
+
+    def to_numpy(self):
+        return (self.offsets.cpu().numpy().view(np.uint64),
+                self.inc_edge.cpu().numpy().view(np.uint32).astype(np.uint64),
+                self.inc_end.cpu().numpy())
+
+
+def adjacency_async(g: Graph, stream=None, result=None, workspace=None) -> Adjacency:
+    """Enqueue the adjacency lists of a built graph (its true row counts must be
+    known on the host: ``g.n_nodes`` / ``g.n_edges``)."""
+    n, m = int(g.n_nodes), int(g.n_edges)
+    dev = g.node_kmer.device
+    offsets = torch.empty(2 * n + 1, dtype=torch.int64, device=dev)
+    inc_edge = torch.empty(max(1, 2 * m), dtype=torch.int32, device=dev)
+    inc_end = torch.empty(max(1, 2 * m), dtype=torch.uint8, device=dev)
+    lib = load()
+    nbytes = int(lib.dbg_adjacency_workspace_bytes(n, m, g.k))
+    if nbytes == 0:
+        raise DbgError(2, "dbg_adjacency_workspace_bytes")
+    ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                              device=dev)
+    res = result if result is not None else torch.zeros(3, dtype=torch.int64, device=dev)
+    rc = lib.dbg_adjacency(_ptr(g.node_kmer), n, _ptr(g.edge_u), _ptr(g.edge_v),
+                           _ptr(g.edge_orient), m, g.k, _ptr(offsets), _ptr(inc_edge),
+                           _ptr(inc_end), _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+    if rc:
+        raise DbgError(rc, "dbg_adjacency")
+    a = Adjacency(offsets, inc_edge[:2 * m], inc_end[:2 * m])
+    a.result = res
+    return a
+
+
+def adjacency(g: Graph) -> Adjacency:
+    """Adjacency lists of a built graph (synchronises; raises on a device error)."""
+    a = adjacency_async(g)
+    _, _, status = read_result(a.result)
+    if status:
+        raise DbgError(status, "dbg_adjacency (device)")
+    return a

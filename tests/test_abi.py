@@ -24,7 +24,8 @@ def lib():
 
 
 def test_header_declares_entry_points():
-    assert declared_functions() == ["dbg_build", "dbg_build_batched", "dbg_get_tuning",
+    assert declared_functions() == ["dbg_adjacency", "dbg_adjacency_workspace_bytes",
+                                    "dbg_build", "dbg_build_batched", "dbg_get_tuning",
                                     "dbg_pack_ascii", "dbg_set_stage_events", "dbg_set_tuning",
                                     "dbg_strerror", "dbg_workspace_bytes"]
 
@@ -97,3 +98,22 @@ def test_tuning_round_trip(lib):
     assert api.get_tuning()["endpoint_ratio"] == pytest.approx(0.25)  # refused: unchanged
     assert lib.dbg_get_tuning(None) == 1
     api.set_tuning(defaults=True)
+
+
+def test_adjacency_host_checks(lib):
+    v = ctypes.c_void_p(256)
+    assert lib.dbg_adjacency_workspace_bytes(10, 20, 30) == 0        # even k
+    assert lib.dbg_adjacency_workspace_bytes(10, 20, 31) > 0
+    args = lambda **kw: dict(dict(nodes=v, n=10, u=v, vv=v, o=v, m=20, k=31, off=v, ie=v, ien=v,
+                                  res=v, ws=v, wsb=1 << 30), **kw)
+    def call(**kw):
+        a = args(**kw)
+        return lib.dbg_adjacency(a["nodes"], a["n"], a["u"], a["vv"], a["o"], a["m"], a["k"],
+                                 a["off"], a["ie"], a["ien"], a["res"], a["ws"], a["wsb"], None)
+    assert call(k=4) == 2                    # DBG_E_K
+    assert call(off=None) == 1               # DBG_E_NULL
+    assert call(u=None) == 1
+    assert call(n=0) == 9                    # edges without nodes: DBG_E_ARG
+    assert call(n=1 << 31) == 4              # DBG_E_OVERFLOW
+    assert call(wsb=16) == 6                 # DBG_E_WORKSPACE
+    assert call(ws=ctypes.c_void_p(257)) == 6

@@ -68,3 +68,29 @@ def test_fullsize_sampled_counts(repeats_full):
     assert np.array_equal(nc[:len(ni)], got["node_count"][ni]), "sampled node counts differ"
     assert (nc[len(ni):] == 0).all(), "a key absent from the node table occurs in the reads"
     assert np.array_equal(ec, got["edge_mult"][ei]), "sampled edge multiplicities differ"
+
+
+def test_fullsize_adjacency(repeats_full):
+    """STEP-4 lists of the full graph: totals, every edge end exactly once, and
+    sampled entries sit in the bucket of their endpoint and orientation."""
+    import torch
+    from paper_1003_1940_amd import api
+    rs, g, got = repeats_full
+    say("[gpu-fullsize] adjacency lists")
+    a = api.adjacency(g)
+    n, m = g.n_nodes, g.n_edges
+    off = a.offsets
+    assert off.numel() == 2 * n + 1 and int(off[0]) == 0 and int(off[-1]) == 2 * m
+    assert bool((off[1:] >= off[:-1]).all())
+    ends = a.inc_edge.to(torch.int64) * 2 + a.inc_end.to(torch.int64)
+    assert bool((torch.bincount(ends, minlength=2 * m) == 1).all())
+    rng = np.random.default_rng(7)
+    pos = torch.from_numpy(rng.choice(2 * m, 4000, replace=False)).cuda()
+    bucket = torch.searchsorted(off, pos, right=True) - 1
+    node, side = bucket // 2, bucket % 2
+    e = a.inc_edge[pos].to(torch.int64)
+    end = a.inc_end[pos].to(torch.int64)
+    key = torch.where(end == 0, g.edge_u[e], g.edge_v[e])
+    assert bool((key == g.node_kmer[node]).all()), "an entry is not at its endpoint's node"
+    o = g.edge_orient[e].to(torch.int64)
+    assert bool((torch.where(end == 0, o >> 1, o & 1) == side).all()), "wrong side"
