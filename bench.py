@@ -447,6 +447,32 @@ def main():
     build_lsd = {"bytes": round(lsd), "achieved": round(lsd_gbs, 1), "unit": "GB/s",
                  "frac": round(lsd_gbs / HBM_PEAK_GBS, 4)}
 
+    # STEP-4 adjacency lists of the built graph (not part of the timed build)
+    adjacency = None
+    if status == 0 and args.cap_frac >= 1.0:  # memory-tight runs leave no room for it
+        g = api.Graph(k, out["node_kmer"], out["node_count"], out["edge_u"], out["edge_v"],
+                      out["edge_orient"], out["edge_mult"], out["edge_zkey"], n_nodes, n_edges, 0)
+        a = api.adjacency(g)  # warm-up (and workspace sizing)
+        ts = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            a = api.adjacency_async(g, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        a_ms = float(np.median(ts))
+        # node keys read once (index build), each edge's endpoints and orientation
+        # read, the two bucket ids written, counted, read back and placed, the
+        # offsets written and read, the entries written and sorted in place
+        a_bytes = (n_nodes * w + n_edges * (2 * w + 1) + 2 * n_edges * 4 * 3
+                   + (2 * n_nodes + 1) * 8 * 2 + 2 * n_edges * 5 * 2)
+        adjacency = {"ms": round(a_ms, 4), "bytes": a_bytes,
+                     "achieved_GBs": round(a_bytes / (a_ms / 1e3) / 1e9, 1)}
+        log(f"adjacency: {adjacency}")
+        del a, g
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
@@ -470,6 +496,7 @@ def main():
         "stages_ms": {k_: round(v, 4) for k_, v in stages.items()},
         "sort_reduce_ms": round(sr_ms, 4),
         "build_as_lsd_d8": build_lsd,
+        "adjacency": adjacency,
         "tuning": tuning if tuning is not None else api.get_tuning(),
         "h2d_upload_and_pack_s": round(h2d_s, 4),
     }
