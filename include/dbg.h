@@ -214,16 +214,23 @@ int dbg_set_tuning(const dbg_tuning_t *tuning);
 /* Copies the current tuning into *tuning (DBG_E_NULL if null). */
 int dbg_get_tuning(dbg_tuning_t *tuning);
 
-/* STEP-4 of Sec. 3: adjacency lists of a built graph.  Each distinct edge
- * (u, v, o1, o2) has two ends, the u end on side o1 of node u and the v end on
- * side o2 of node v ('+' = 0, '-' = 1); a self-loop gives its node two ends.  The
- * lists group the ends by (node, side) -- nodes in node-table order, side '+'
- * first -- and order each group by edge row, u end first.  Output as a CSR over
- * the 2 n_nodes buckets b = 2 * node + side:
+/* STEP-4 of Sec. 3: adjacency lists of a built graph.  A node has two sides:
+ * side 0, by which a walk reading its canonical k-mer forward leaves it, and
+ * side 1, by which such a walk enters it.  A distinct edge (u, v, o1, o2) leaves
+ * u by side o1 and enters v by side 1 - o2 ('+' = 0, '-' = 1), so its u end lies
+ * on side o1 of u and its v end on side 1 - o2 of v; a self-loop gives its node
+ * two ends.  (The sides are the same when the record is written with its
+ * endpoints swapped, as the STEP-1 table's ELSE branches do, and a walk through
+ * a node uses one end on each side: the walk rule of Sec. 2.)  The lists group
+ * the ends by (node, side) -- nodes in node-table order, side 0 first -- and
+ * order each group by edge row, u end first.  Output as a CSR over the 2 n_nodes
+ * buckets b = 2 * node + side:
  *   offsets   device, 2 n_nodes + 1 uint64_t: bucket b holds entries
  *             offsets[b] .. offsets[b + 1] - 1;
  *   inc_edge  device, 2 n_edges uint32_t: edge row of each entry;
- *   inc_end   device, 2 n_edges bytes: 0 for the u end, 1 for the v end.
+ *   inc_end   device, 2 n_edges bytes: 0 for the u end, 1 for the v end;
+ *   edge_node device, 2 n_edges uint32_t, or NULL: node rows of the u end and
+ *             the v end of every edge (edge_node[2 j], edge_node[2 j + 1]).
  * Inputs are a build's tables (device): node_kmer (n_nodes keys, ascending),
  * edge_u / edge_v / edge_orient (n_edges rows), key width as in dbg_build; the
  * counts are the build's n_nodes / n_edges (read from its result record).
@@ -235,8 +242,9 @@ int dbg_get_tuning(dbg_tuning_t *tuning);
 size_t dbg_adjacency_workspace_bytes(uint64_t n_nodes, uint64_t n_edges, int k);
 int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
                   const void *edge_v, const uint8_t *edge_orient, uint64_t n_edges, int k,
-                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, dbg_result_t *result,
-                  void *workspace, size_t workspace_bytes, hipStream_t stream);
+                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, uint32_t *edge_node,
+                  dbg_result_t *result, void *workspace, size_t workspace_bytes,
+                  hipStream_t stream);
 
 /* Static description of a status code. */
 const char *dbg_strerror(int status);

@@ -2,14 +2,23 @@
 bi-directed de Bruijn graph, from the node table and the edge list of the oracle.
 
 Reading (the paper leaves the representation open): every distinct edge
-(u, v, o1, o2) has two ends, the u end carrying arrowhead orientation o1 and the v
-end carrying o2 ('+' = 0, '-' = 1).  Each end is an incidence of its node on the
-side named by its orientation; a self-loop gives its node two incidences.  The
-adjacency lists are the incidences grouped by (node, side), nodes in node-table
-order and side '+' before '-', and ordered inside a group by edge row, u end
-first.  As a CSR: offsets[2 i + s] .. offsets[2 i + s + 1] index the entries
-(edge row, end) of node i's side s; there are 2 n_nodes + 1 offsets and
-2 n_edges entries.
+(u, v, o1, o2) has two ends, one at u and one at v.  A node has two sides: side
+0 is the end of its canonical k-mer that a walk reading the k-mer forward leaves
+by (its suffix end), side 1 the end such a walk enters by (its prefix end).  The
+STEP-1 record of a (k+1)-mer z = x.c with y = z[2..k+1] says how z passes the two
+nodes: o1 = '+' when x is read forward, so the walk leaves u by side 0, and by
+side 1 when o1 = '-'; o2 = '+' when y is read forward, so the walk enters v by
+side 1, and by side 0 when o2 = '-'.  Hence the u end lies on side o1 and the v
+end on side 1 - o2 ('+' = 0, '-' = 1).  The same sides result when the record
+is written the other way round, (v, u, not o2, not o1), as the ELSE branches of
+STEP-1 write it, so the side of an end does not depend on which endpoint the
+record lists first.  A walk through a node uses one end on each side (the
+walk rule of Sec. 2, read as the arrowheads' direction into or out of the node).
+A self-loop gives its node two ends.  The adjacency lists are the ends grouped
+by (node, side), nodes in node-table order and side 0 before side 1, and
+ordered inside a group by edge row, u end first.  As a CSR: offsets[2 i + s] ..
+offsets[2 i + s + 1] index the entries (edge row, end) of node i's side s; there
+are 2 n_nodes + 1 offsets and 2 n_edges entries.
 
 Written with plain Python lists and tuples (one sort); it shares nothing with the
 GPU library.
@@ -32,7 +41,7 @@ def adjacency(node_key, edge_u, edge_v, edge_orient):
         iu = index[(int(edge_u[j][0]), int(edge_u[j][1]))]
         iv = index[(int(edge_v[j][0]), int(edge_v[j][1]))]
         recs.append((iu, o >> 1, j, 0))
-        recs.append((iv, o & 1, j, 1))
+        recs.append((iv, 1 - (o & 1), j, 1))
     recs.sort()
     counts = [0] * (2 * n)
     for node, side, _, _ in recs:

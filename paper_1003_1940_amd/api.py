@@ -80,7 +80,8 @@ def load():
         lib.dbg_adjacency_workspace_bytes.restype = sz
         lib.dbg_adjacency_workspace_bytes.argtypes = [u64, u64, i32]
         lib.dbg_adjacency.restype = i32
-        lib.dbg_adjacency.argtypes = [vp, u64, vp, vp, vp, u64, i32, vp, vp, vp, vp, vp, sz, vp]
+        lib.dbg_adjacency.argtypes = [vp, u64, vp, vp, vp, u64, i32, vp, vp, vp, vp, vp, vp, sz,
+                                      vp]
         lib.dbg_strerror.restype = ctypes.c_char_p
         lib.dbg_strerror.argtypes = [i32]
         _lib = lib
@@ -408,11 +409,14 @@ class CapturedBuild:
 
 @dataclass
 class Adjacency:
-    """STEP-4 adjacency lists as a CSR over buckets b = 2 * node + side: entries
-    offsets[b] .. offsets[b+1] of (edge row, end), end 0 = the u end."""
+    """STEP-4 adjacency lists as a CSR over buckets b = 2 * node + side (side 0:
+    left by a walk reading the canonical k-mer forward, side 1: entered by it):
+    entries offsets[b] .. offsets[b+1] of (edge row, end), end 0 = the u end.
+    ``edge_node`` holds the node rows of both ends of every edge."""
     offsets: torch.Tensor    # int64, 2 n_nodes + 1
     inc_edge: torch.Tensor   # int32 holding uint32 edge rows, 2 n_edges
     inc_end: torch.Tensor    # uint8, 2 n_edges
+    edge_node: torch.Tensor | None = None  # int32 holding uint32 node rows, 2 n_edges
 
     def to_numpy(self):
         return (self.offsets.cpu().numpy().view(np.uint64),
@@ -420,14 +424,17 @@ class Adjacency:
                 self.inc_end.cpu().numpy())
 
 
-def adjacency_async(g: Graph, stream=None, result=None, workspace=None) -> Adjacency:
+def adjacency_async(g: Graph, stream=None, result=None, workspace=None,
+                    edge_nodes: bool = False) -> Adjacency:
     """Enqueue the adjacency lists of a built graph (its true row counts must be
-    known on the host: ``g.n_nodes`` / ``g.n_edges``)."""
+    known on the host: ``g.n_nodes`` / ``g.n_edges``); ``edge_nodes`` also
+    returns the node rows of every edge's ends."""
     n, m = int(g.n_nodes), int(g.n_edges)
     dev = g.node_kmer.device
     offsets = torch.empty(2 * n + 1, dtype=torch.int64, device=dev)
     inc_edge = torch.empty(max(1, 2 * m), dtype=torch.int32, device=dev)
     inc_end = torch.empty(max(1, 2 * m), dtype=torch.uint8, device=dev)
+    enode = torch.empty(max(1, 2 * m), dtype=torch.int32, device=dev) if edge_nodes else None
     lib = load()
     nbytes = int(lib.dbg_adjacency_workspace_bytes(n, m, g.k))
     if nbytes == 0:
@@ -437,17 +444,19 @@ def adjacency_async(g: Graph, stream=None, result=None, workspace=None) -> Adjac
     res = result if result is not None else torch.zeros(3, dtype=torch.int64, device=dev)
     rc = lib.dbg_adjacency(_ptr(g.node_kmer), n, _ptr(g.edge_u), _ptr(g.edge_v),
                            _ptr(g.edge_orient), m, g.k, _ptr(offsets), _ptr(inc_edge),
-                           _ptr(inc_end), _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+                           _ptr(inc_end), _ptr(enode) if enode is not None else None, _ptr(res),
+                           _ptr(ws), ws.numel(), _stream(stream))
     if rc:
         raise DbgError(rc, "dbg_adjacency")
-    a = Adjacency(offsets, inc_edge[:2 * m], inc_end[:2 * m])
+    a = Adjacency(offsets, inc_edge[:2 * m], inc_end[:2 * m],
+                  enode[:2 * m] if enode is not None else None)
     a.result = res
     return a
 
 
-def adjacency(g: Graph) -> Adjacency:
+def adjacency(g: Graph, edge_nodes: bool = False) -> Adjacency:
     """Adjacency lists of a built graph (synchronises; raises on a device error)."""
-    a = adjacency_async(g)
+    a = adjacency_async(g, edge_nodes=edge_nodes)
     _, _, status = read_result(a.result)
     if status:
         raise DbgError(status, "dbg_adjacency (device)")

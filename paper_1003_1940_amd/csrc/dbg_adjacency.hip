@@ -1,11 +1,17 @@
 // STEP-4 of Sec. 3: adjacency lists of the bi-directed graph from its node table
 // and edge list.
 //
-// Every distinct edge (u, v, o1, o2) has two ends: the u end on side o1 of node
-// u and the v end on side o2 of node v.  The lists group these incidences by
-// (node, side), nodes in table order and side '+' (0) before '-' (1), and order
-// each group by edge row, u end first.  As a CSR: bucket b = 2 * node + side
-// holds entries offsets[b] .. offsets[b + 1] of (edge row, end).
+// A node has two sides: side 0, by which a walk reading its canonical k-mer
+// forward leaves it, and side 1, by which such a walk enters it.  The record
+// (u, v, o1, o2) of a (k+1)-mer leaves u by side 0 when o1 = '+' (side 1 when
+// '-') and enters v by side 1 when o2 = '+' (side 0 when '-'): its u end lies on
+// side o1 and its v end on side 1 - o2 ('+' = 0).  These sides do not change when
+// a record is written with its endpoints swapped, (v, u, not o2, not o1), as the
+// STEP-1 table does in its ELSE branches.  The lists group the ends by (node,
+// side), nodes in table order and side 0 first, and order each group by edge
+// row, u end first.  As a CSR: bucket b = 2 * node + side holds entries
+// offsets[b] .. offsets[b + 1] of (edge row, end).  Optionally the node rows of
+// both ends of every edge are returned as well.
 //
 //   1. k_adj_index: a prefix index over the sorted node keys (first row of every
 //      B-bit key prefix), so an endpoint is found by one index read and a
@@ -72,7 +78,7 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_count(const K *keys, uint64_t n,
                                                       const K *eu, const K *ev,
                                                       const uint8_t *orient, uint64_t m,
                                                       uint32_t *bucket, uint32_t *counts,
-                                                      dbg_result_t *res) {
+                                                      uint32_t *edge_node, dbg_result_t *res) {
   for (uint64_t j = blockIdx.x * (uint64_t)ADJ_NT + threadIdx.x; j < m;
        j += (uint64_t)gridDim.x * ADJ_NT) {
     const uint32_t o = orient[j];
@@ -83,9 +89,13 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_count(const K *keys, uint64_t n,
       bucket[2 * j] = bucket[2 * j + 1] = 0xffffffffu;
       continue;
     }
-    const uint32_t bu = (uint32_t)(2 * iu + (o >> 1)), bv = (uint32_t)(2 * iv + (o & 1u));
+    const uint32_t bu = (uint32_t)(2 * iu + (o >> 1)), bv = (uint32_t)(2 * iv + ((o & 1u) ^ 1u));
     bucket[2 * j] = bu;
     bucket[2 * j + 1] = bv;
+    if (edge_node) {
+      edge_node[2 * j] = (uint32_t)iu;
+      edge_node[2 * j + 1] = (uint32_t)iv;
+    }
     atomicAdd(&counts[bu], 1u);
     atomicAdd(&counts[bv], 1u);
   }
@@ -237,7 +247,8 @@ template <typename K>
 static hipError_t run_adjacency(const void *node_kmer, uint64_t n, const void *eu, const void *ev,
                                 const uint8_t *orient, uint64_t m, const AdjLayout &L,
                                 uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end,
-                                dbg_result_t *res, char *ws, hipStream_t st) {
+                                uint32_t *edge_node, dbg_result_t *res, char *ws,
+                                hipStream_t st) {
   const K *keys = static_cast<const K *>(node_kmer);
   uint32_t *first = reinterpret_cast<uint32_t *>(ws + L.first);
   uint32_t *bucket = reinterpret_cast<uint32_t *>(ws + L.bucket);
@@ -251,7 +262,7 @@ static hipError_t run_adjacency(const void *node_kmer, uint64_t n, const void *e
                      L.shift, L.nbins, first);
   hipLaunchKernelGGL(k_adj_count<K>, dim3(adj_grid(m, 16384)), dim3(ADJ_NT), 0, st, keys, n,
                      first, L.nbins, L.shift, static_cast<const K *>(eu), static_cast<const K *>(ev),
-                     orient, m, bucket, counts, res);
+                     orient, m, bucket, counts, edge_node, res);
   hipLaunchKernelGGL(k_adj_scan_reduce, dim3((unsigned)nsum), dim3(ADJ_NT), 0, st, counts, nb,
                      sums);
   hipLaunchKernelGGL(k_adj_scan_sums, dim3(1), dim3(1024), 0, st, sums, nsum);
@@ -276,8 +287,9 @@ size_t dbg_adjacency_workspace_bytes(uint64_t n_nodes, uint64_t n_edges, int k) 
 
 int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
                   const void *edge_v, const uint8_t *edge_orient, uint64_t n_edges, int k,
-                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, dbg_result_t *result,
-                  void *workspace, size_t workspace_bytes, hipStream_t stream) {
+                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, uint32_t *edge_node,
+                  dbg_result_t *result, void *workspace, size_t workspace_bytes,
+                  hipStream_t stream) {
   if (k < 1 || k > 63 || (k & 1) == 0) return DBG_E_K;
   if (!offsets || !result || !workspace) return DBG_E_NULL;
   if (n_nodes && !node_kmer) return DBG_E_NULL;
@@ -290,11 +302,11 @@ int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
   char *ws = static_cast<char *>(workspace);
   const hipError_t e =
       k <= 31 ? dbg::run_adjacency<uint64_t>(node_kmer, n_nodes, edge_u, edge_v, edge_orient,
-                                             n_edges, L, offsets, inc_edge, inc_end, result, ws,
-                                             stream)
+                                             n_edges, L, offsets, inc_edge, inc_end, edge_node,
+                                             result, ws, stream)
               : dbg::run_adjacency<unsigned __int128>(node_kmer, n_nodes, edge_u, edge_v,
                                                       edge_orient, n_edges, L, offsets, inc_edge,
-                                                      inc_end, result, ws, stream);
+                                                      inc_end, edge_node, result, ws, stream);
   return e == hipSuccess ? DBG_OK : DBG_E_HIP;
 }
 

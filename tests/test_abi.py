@@ -109,7 +109,8 @@ def test_adjacency_host_checks(lib):
     def call(**kw):
         a = args(**kw)
         return lib.dbg_adjacency(a["nodes"], a["n"], a["u"], a["vv"], a["o"], a["m"], a["k"],
-                                 a["off"], a["ie"], a["ien"], a["res"], a["ws"], a["wsb"], None)
+                                 a["off"], a["ie"], a["ien"], None, a["res"], a["ws"], a["wsb"],
+                                 None)
     assert call(k=4) == 2                    # DBG_E_K
     assert call(off=None) == 1               # DBG_E_NULL
     assert call(u=None) == 1

@@ -14,7 +14,7 @@ from oracle import adjacency as adj_mod
 from paper_1003_1940_amd import synth
 from . import keys_np as K
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "step4_adjacency_v3.txt")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "step4_adjacency_sides.txt")
 
 
 def _golden():
@@ -30,6 +30,43 @@ def _golden():
 def _graph(reads, k):
     rs = synth.from_strings(reads)
     return rs, oracle.build_graph(rs.bases, rs.offsets, k)
+
+
+def _node_index(g):
+    return {(int(a), int(b)): i for i, (a, b) in enumerate(g.node_key)}
+
+
+def _check_walk_sides(g, rs, offsets, inc_edge, inc_end):
+    k = g.k
+    if not rs.n_bases:
+        return
+    idx = _node_index(g)
+    codes = K.codes(rs.bases[:rs.n_bases])
+    off = rs.offsets.astype(np.int64)
+    starts = np.concatenate([np.arange(off[i], off[i + 1] - k) for i in range(len(off) - 1)
+                             if off[i + 1] - off[i] >= k + 1] or [np.zeros(0, np.int64)])
+    if not len(starts):
+        return
+    xl, xh = K.window_keys(codes, starts, k)
+    yl, yh = K.window_keys(codes, starts + 1, k)
+    xcl, xch, xflip = K.canonical(xl, xh, k)
+    ycl, ych, yflip = K.canonical(yl, yh, k)
+    off = offsets.astype(np.int64)
+
+    def bucket_ends(node, side):
+        b = 2 * node + side
+        return {(int(inc_edge[t]), int(inc_end[t])) for t in range(off[b], off[b + 1])}
+
+    for t in range(len(starts)):
+        a = idx[(int(xcl[t]), int(xch[t]))]
+        b = idx[(int(ycl[t]), int(ych[t]))]
+        out_side = 1 if xflip[t] else 0
+        in_side = 0 if yflip[t] else 1
+        ea = bucket_ends(a, out_side)
+        eb = bucket_ends(b, in_side)
+        # one edge row with one end in each bucket (two different ends of the row)
+        ok = any((r, 1 - e) in eb for r, e in ea)
+        assert ok, f"no edge joins node {a} side {out_side} to node {b} side {in_side}"
 
 
 def check_adjacency(g, rs, offsets, inc_edge, inc_end):
@@ -49,8 +86,12 @@ def check_adjacency(g, rs, offsets, inc_edge, inc_end):
     j = inc_edge.astype(np.int64)
     ends = np.where(inc_end[:, None] == 0, g.edge_u[j], g.edge_v[j])
     assert (ends == g.node_key[node]).all()
-    o = g.edge_orient[j]
-    assert (np.where(inc_end == 0, o >> 1, o & 1) == side).all()
+    # sides from the reads themselves: for every (k+1)-mer window x.c of a read,
+    # with y its last k bases, some edge has an end on the side of x's node that a
+    # walk reading x in the read's direction leaves by (0 when x is canonical, 1
+    # otherwise) and its other end on the side of y's node that the walk enters
+    # by (1 when y is canonical, 0 otherwise)
+    _check_walk_sides(g, rs, offsets, inc_edge, inc_end)
     # inside a bucket, (edge, end) strictly ascending
     key = j * 2 + inc_end
     same = bucket[1:] == bucket[:-1]
@@ -113,9 +154,12 @@ def test_invariants_random_and_workload():
 MUTANTS = {
     "ends_swapped": ("recs.append((iu, o >> 1, j, 0))", "recs.append((iu, o >> 1, j, 1))"),
     "orientations_swapped": ("recs.append((iu, o >> 1, j, 0))", "recs.append((iu, o & 1, j, 0))"),
+    "v_end_on_arrowhead_value": ("recs.append((iv, 1 - (o & 1), j, 1))",
+                                 "recs.append((iv, o & 1, j, 1))"),
+    "u_end_side_flipped": ("recs.append((iu, o >> 1, j, 0))", "recs.append((iu, 1 - (o >> 1), j, 0))"),
     "side_major_order": ("recs.sort()", "recs.sort(key=lambda r: (r[1], r[0], r[2], r[3]))"),
-    "self_loop_once": ("recs.append((iv, o & 1, j, 1))",
-                       "recs.append((iv, o & 1, j, 1)) if iv != iu else None"),
+    "self_loop_once": ("recs.append((iv, 1 - (o & 1), j, 1))",
+                       "recs.append((iv, 1 - (o & 1), j, 1)) if iv != iu else None"),
     "offsets_shifted": ("offsets[b + 1] = offsets[b] + counts[b]",
                         "offsets[b + 1] = offsets[b] + counts[b - 1] if b else 0"),
 }

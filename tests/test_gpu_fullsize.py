@@ -72,7 +72,7 @@ def test_fullsize_sampled_counts(repeats_full):
 
 def test_fullsize_adjacency(repeats_full):
     """STEP-4 lists of the full graph: totals, every edge end exactly once, and
-    sampled entries sit in the bucket of their endpoint and orientation."""
+    sampled entries sit in the bucket of their endpoint and side."""
     import torch
     from paper_1003_1940_amd import api
     rs, g, got = repeats_full
@@ -93,4 +93,5 @@ def test_fullsize_adjacency(repeats_full):
     key = torch.where(end == 0, g.edge_u[e], g.edge_v[e])
     assert bool((key == g.node_kmer[node]).all()), "an entry is not at its endpoint's node"
     o = g.edge_orient[e].to(torch.int64)
-    assert bool((torch.where(end == 0, o >> 1, o & 1) == side).all()), "wrong side"
+    # the u end lies on side o1, the v end on side 1 - o2
+    assert bool((torch.where(end == 0, o >> 1, 1 - (o & 1)) == side).all()), "wrong side"
