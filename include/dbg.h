@@ -246,6 +246,78 @@ int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
                   dbg_result_t *result, void *workspace, size_t workspace_bytes,
                   hipStream_t stream);
 
+/* Bi-directed chain compaction (Sec. 7): the simplified graph of a built graph.
+ * Sides are those of dbg_adjacency.  An edge is a candidate when it is not a
+ * self-loop and each of its ends is the only end on its side (the paper's "one
+ * in- and one out-edge" criterion, read per edge end).  ListRankingTransform
+ * gives every node v a forward copy v+ and a reverse-complement copy v-; the
+ * candidates link the copies into lists and cycles, which are ranked by pointer
+ * jumping; a cycle is broken at its smallest node, starting at v+.  Of a chain's
+ * two copies the one whose first k-mer is smaller is kept (for a broken cycle,
+ * the one starting at v+).  Chains shorter than min_nodes are not merged (the
+ * paper keeps chains of three or more nodes; 0 and 1 keep all).
+ *
+ * Output (device buffers owned by the caller):
+ *   node_chain, node_rank  n_nodes uint32_t: chain of every node and its
+ *                          position along the chain's walk;
+ *   node_orient            n_nodes bytes: 0 when the walk reads the node's
+ *                          canonical k-mer forward, 1 when reverse-complemented;
+ *   chain_head, chain_len  capacity n_nodes uint32_t: first node (row) and node
+ *                          count of every chain; chains are numbered in the order
+ *                          of their first node, a node alone is a chain of one;
+ *   chain_cyclic           capacity n_nodes bytes: 1 for a broken cycle;
+ *   label_offsets          n_nodes + 1 uint64_t: chain c spells
+ *                          labels[label_offsets[c] .. label_offsets[c + 1]),
+ *                          k + chain_len - 1 ASCII bases (A, C, G, T);
+ *   labels, label_capacity at most label_capacity bytes (n_chains * (k - 1) +
+ *                          n_nodes are written; n_nodes * k always suffices);
+ *   kept_row, kept_u,      capacity n_edges: every edge that is not merged into
+ *   kept_v, kept_orient    a chain, in row order: its row, the chains of its u
+ *                          and v ends, and (o1 << 1) | o2 on chain sides (an end
+ *                          on side s of a node with orientation t lies on side
+ *                          s xor t of its chain; o1 = side at u, o2 = 1 - side
+ *                          at v, as in the input edges).
+ * Inputs (device): the build's node_kmer (ascending) and edge_orient with their
+ * true counts, and dbg_adjacency's offsets, inc_edge, inc_end and edge_node of
+ * the same graph.  result (device) receives n_chains, n_kept, label_len,
+ * n_cyclic (cycles broken, before min_nodes) and status: DBG_OK, DBG_E_ARG (an
+ * input row out of range), DBG_E_CAPACITY (labels longer than label_capacity:
+ * no label byte written) or DBG_E_INTERNAL (ranking did not finish: a bug).
+ * Host errors: DBG_E_K, DBG_E_NULL, DBG_E_ARG (edges without nodes),
+ * DBG_E_OVERFLOW (n_nodes >= 2^31 or n_edges >= 2^32), DBG_E_WORKSPACE.
+ * Enqueues on `stream`, never synchronises or allocates. */
+typedef struct {
+  uint32_t *node_chain;
+  uint32_t *node_rank;
+  uint8_t *node_orient;
+  uint32_t *chain_head;
+  uint32_t *chain_len;
+  uint8_t *chain_cyclic;
+  uint64_t *label_offsets;
+  uint8_t *labels;
+  uint64_t label_capacity;
+  uint32_t *kept_row;
+  uint32_t *kept_u;
+  uint32_t *kept_v;
+  uint8_t *kept_orient;
+} dbg_chains_t;
+
+typedef struct {
+  uint64_t n_chains;  /* chains, single nodes included */
+  uint64_t n_kept;    /* edges not merged into a chain */
+  uint64_t label_len; /* bases of all labels */
+  uint64_t n_cyclic;  /* cycles broken open (before min_nodes) */
+  uint32_t status;
+  uint32_t pad;
+} dbg_compact_result_t;
+
+size_t dbg_compact_workspace_bytes(uint64_t n_nodes, uint64_t n_edges);
+int dbg_compact(const void *node_kmer, uint64_t n_nodes, const uint8_t *edge_orient,
+                uint64_t n_edges, int k, const uint64_t *adj_offsets, const uint32_t *inc_edge,
+                const uint8_t *inc_end, const uint32_t *edge_node, uint32_t min_nodes,
+                const dbg_chains_t *out, dbg_compact_result_t *result, void *workspace,
+                size_t workspace_bytes, hipStream_t stream);
+
 /* Static description of a status code. */
 const char *dbg_strerror(int status);
 

@@ -46,6 +46,16 @@ class _Tuning(ctypes.Structure):
                 ("reserved", ctypes.c_int * 4)]
 
 
+class _Chains(ctypes.Structure):
+    _fields_ = [("node_chain", ctypes.c_void_p), ("node_rank", ctypes.c_void_p),
+                ("node_orient", ctypes.c_void_p), ("chain_head", ctypes.c_void_p),
+                ("chain_len", ctypes.c_void_p), ("chain_cyclic", ctypes.c_void_p),
+                ("label_offsets", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("label_capacity", ctypes.c_uint64), ("kept_row", ctypes.c_void_p),
+                ("kept_u", ctypes.c_void_p), ("kept_v", ctypes.c_void_p),
+                ("kept_orient", ctypes.c_void_p)]
+
+
 TUNING_FIELDS = ("node_path", "endpoint_ratio", "local_variant", "lds_digit_bias")
 
 
@@ -82,6 +92,11 @@ def load():
         lib.dbg_adjacency.restype = i32
         lib.dbg_adjacency.argtypes = [vp, u64, vp, vp, vp, u64, i32, vp, vp, vp, vp, vp, vp, sz,
                                       vp]
+        lib.dbg_compact_workspace_bytes.restype = sz
+        lib.dbg_compact_workspace_bytes.argtypes = [u64, u64]
+        lib.dbg_compact.restype = i32
+        lib.dbg_compact.argtypes = [vp, u64, vp, u64, i32, vp, vp, vp, vp, ctypes.c_uint32,
+                                    ctypes.POINTER(_Chains), vp, vp, sz, vp]
         lib.dbg_strerror.restype = ctypes.c_char_p
         lib.dbg_strerror.argtypes = [i32]
         _lib = lib
@@ -461,3 +476,101 @@ def adjacency(g: Graph, edge_nodes: bool = False) -> Adjacency:
     if status:
         raise DbgError(status, "dbg_adjacency (device)")
     return a
+
+
+@dataclass
+class Chains:
+    """Simplified graph (Sec. 7 chain compaction) on the device; uint32 values
+    are held in int32 tensors.  Chain c spells
+    labels[label_offsets[c]:label_offsets[c + 1]] (ASCII)."""
+    node_chain: torch.Tensor    # n_nodes
+    node_rank: torch.Tensor     # n_nodes
+    node_orient: torch.Tensor   # n_nodes, uint8
+    chain_head: torch.Tensor    # n_chains
+    chain_len: torch.Tensor     # n_chains
+    chain_cyclic: torch.Tensor  # n_chains, uint8
+    label_offsets: torch.Tensor  # n_chains + 1, int64
+    labels: torch.Tensor        # label_len, uint8
+    kept_row: torch.Tensor      # n_kept
+    kept_u: torch.Tensor
+    kept_v: torch.Tensor
+    kept_orient: torch.Tensor   # uint8
+    n_chains: int = -1
+    n_kept: int = -1
+    label_len: int = -1
+    n_cyclic: int = -1
+    result: torch.Tensor | None = None
+    _full: dict = field(default_factory=dict)
+
+    def finish(self):
+        """Read the result record (synchronises) and trim the tables; raises on
+        a device error."""
+        r = self.result.cpu().numpy().view(np.uint64)
+        status = int(r[4] & 0xFFFFFFFF)
+        if status:
+            raise DbgError(status, "dbg_compact (device)")
+        self.n_chains, self.n_kept, self.label_len, self.n_cyclic = (int(x) for x in r[:4])
+        f = self._full
+        self.chain_head = f["chain_head"][:self.n_chains]
+        self.chain_len = f["chain_len"][:self.n_chains]
+        self.chain_cyclic = f["chain_cyclic"][:self.n_chains]
+        self.label_offsets = f["label_offsets"][:self.n_chains + 1]
+        self.labels = f["labels"][:self.label_len]
+        self.kept_row = f["kept_row"][:self.n_kept]
+        self.kept_u = f["kept_u"][:self.n_kept]
+        self.kept_v = f["kept_v"][:self.n_kept]
+        self.kept_orient = f["kept_orient"][:self.n_kept]
+        return self
+
+    def label(self, c: int) -> str:
+        off = self.label_offsets
+        return bytes(self.labels[int(off[c]):int(off[c + 1])].cpu().numpy()).decode()
+
+
+def alloc_chains(n: int, m: int, k: int, device="cuda", label_capacity: int | None = None):
+    """Output buffers of dbg_compact for a graph of n nodes and m edges."""
+    i32, u8 = torch.int32, torch.uint8
+    cap = n * k if label_capacity is None else int(label_capacity)
+    z = lambda cnt, dt: torch.empty(max(1, cnt), dtype=dt, device=device)
+    return {"node_chain": z(n, i32), "node_rank": z(n, i32), "node_orient": z(n, u8),
+            "chain_head": z(n, i32), "chain_len": z(n, i32), "chain_cyclic": z(n, u8),
+            "label_offsets": z(n + 1, torch.int64), "labels": z(cap, u8),
+            "kept_row": z(m, i32), "kept_u": z(m, i32), "kept_v": z(m, i32),
+            "kept_orient": z(m, u8)}
+
+
+def compact_async(g: Graph, adj: Adjacency, min_nodes: int = 3, stream=None, out=None,
+                  workspace=None, result=None, label_capacity: int | None = None) -> Chains:
+    """Enqueue the chain compaction of a built graph from its adjacency lists
+    (``adj`` must hold ``edge_node``: ``adjacency(g, edge_nodes=True)``)."""
+    n, m = int(g.n_nodes), int(g.n_edges)
+    if adj.edge_node is None and m:
+        raise ValueError("the adjacency lists need edge_node (adjacency(g, edge_nodes=True))")
+    dev = g.node_kmer.device
+    out = out if out is not None else alloc_chains(n, m, g.k, dev, label_capacity)
+    lib = load()
+    nbytes = int(lib.dbg_compact_workspace_bytes(n, m))
+    ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                              device=dev)
+    res = result if result is not None else torch.zeros(5, dtype=torch.int64, device=dev)
+    st = _Chains(*[out[f].data_ptr() if f != "label_capacity" else out["labels"].numel()
+                   for f, _ in _Chains._fields_])
+    rc = lib.dbg_compact(_ptr(g.node_kmer), n, _ptr(g.edge_orient), m, g.k, _ptr(adj.offsets),
+                         _ptr(adj.inc_edge), _ptr(adj.inc_end),
+                         _ptr(adj.edge_node) if adj.edge_node is not None else None,
+                         int(min_nodes), ctypes.byref(st), _ptr(res), _ptr(ws), ws.numel(),
+                         _stream(stream))
+    if rc:
+        raise DbgError(rc, "dbg_compact")
+    c = Chains(out["node_chain"][:n], out["node_rank"][:n], out["node_orient"][:n],
+               out["chain_head"], out["chain_len"], out["chain_cyclic"], out["label_offsets"],
+               out["labels"], out["kept_row"], out["kept_u"], out["kept_v"], out["kept_orient"],
+               result=res, _full=out)
+    c.workspace = ws
+    return c
+
+
+def compact(g: Graph, adj: Adjacency | None = None, min_nodes: int = 3) -> Chains:
+    """Chain compaction of a built graph (synchronises; raises on a device error)."""
+    adj = adj if adj is not None else adjacency(g, edge_nodes=True)
+    return compact_async(g, adj, min_nodes).finish()

@@ -8,7 +8,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdbg.so")
-SOURCES = ["dbg_kernels.hip", "dbg_api.hip", "dbg_adjacency.hip"]
+SOURCES = ["dbg_kernels.hip", "dbg_api.hip", "dbg_adjacency.hip", "dbg_compact.hip"]
 ARCH = "gfx950"
 
 

@@ -25,7 +25,8 @@ def lib():
 
 def test_header_declares_entry_points():
     assert declared_functions() == ["dbg_adjacency", "dbg_adjacency_workspace_bytes",
-                                    "dbg_build", "dbg_build_batched", "dbg_get_tuning",
+                                    "dbg_build", "dbg_build_batched", "dbg_compact",
+                                    "dbg_compact_workspace_bytes", "dbg_get_tuning",
                                     "dbg_pack_ascii", "dbg_set_stage_events", "dbg_set_tuning",
                                     "dbg_strerror", "dbg_workspace_bytes"]
 
@@ -117,4 +118,30 @@ def test_adjacency_host_checks(lib):
     assert call(n=0) == 9                    # edges without nodes: DBG_E_ARG
     assert call(n=1 << 31) == 4              # DBG_E_OVERFLOW
     assert call(wsb=16) == 6                 # DBG_E_WORKSPACE
+    assert call(ws=ctypes.c_void_p(257)) == 6
+
+
+def test_compact_host_checks(lib):
+    """dbg_compact's argument checks on the host (no device work is enqueued)."""
+    from paper_1003_1940_amd import api
+    assert lib.dbg_compact_workspace_bytes(10, 20) > 0
+    assert lib.dbg_compact_workspace_bytes(0, 0) > 0
+    v = 256
+    full = api._Chains(*[v if f != "label_capacity" else 1000 for f, _ in api._Chains._fields_])
+    no_labels = api._Chains(*[v if f not in ("labels", "label_capacity") else (0 if f == "labels"
+                                                                               else 1000)
+                              for f, _ in api._Chains._fields_])
+    vp = ctypes.c_void_p(256)
+
+    def call(n=10, m=20, k=31, out=full, ws=vp, wsb=1 << 30, enode=vp, res=vp):
+        return lib.dbg_compact(vp, n, vp, m, k, vp, vp, vp, enode, 3,
+                               ctypes.byref(out) if out is not None else None, res, ws, wsb, None)
+    assert call(k=4) == 2                     # DBG_E_K
+    assert call(out=None) == 1                # DBG_E_NULL
+    assert call(res=None) == 1
+    assert call(out=no_labels) == 1           # labels needed with nodes
+    assert call(enode=None) == 1              # edge_node needed with edges
+    assert call(n=0) == 9                     # edges without nodes: DBG_E_ARG
+    assert call(n=1 << 31) == 4               # DBG_E_OVERFLOW
+    assert call(wsb=16) == 6                  # DBG_E_WORKSPACE
     assert call(ws=ctypes.c_void_p(257)) == 6
