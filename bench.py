@@ -447,31 +447,48 @@ def main():
     build_lsd = {"bytes": round(lsd), "achieved": round(lsd_gbs, 1), "unit": "GB/s",
                  "frac": round(lsd_gbs / HBM_PEAK_GBS, 4)}
 
-    # STEP-4 adjacency lists of the built graph (not part of the timed build)
-    adjacency = None
-    if status == 0 and args.cap_frac >= 1.0:  # memory-tight runs leave no room for it
+    # STEP-4 adjacency lists and the Sec. 7 chain compaction of the built graph
+    # (not part of the timed build)
+    adjacency = compaction = None
+    if status == 0 and args.cap_frac >= 1.0:  # memory-tight runs leave no room for them
         g = api.Graph(k, out["node_kmer"], out["node_count"], out["edge_u"], out["edge_v"],
                       out["edge_orient"], out["edge_mult"], out["edge_zkey"], n_nodes, n_edges, 0)
-        a = api.adjacency(g)  # warm-up (and workspace sizing)
-        ts = []
-        for _ in range(5):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            a = api.adjacency_async(g, stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        a_ms = float(np.median(ts))
+
+        def timed(fn, reps=5):
+            ts, r = [], None
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                r = fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return float(np.median(ts)), r
+
+        a = api.adjacency(g, edge_nodes=True)  # warm-up (and workspace sizing)
+        a_ms, a = timed(lambda: api.adjacency_async(g, stream, edge_nodes=True))
         # node keys read once (index build), each edge's endpoints and orientation
         # read, the two bucket ids written, counted, read back and placed, the
-        # offsets written and read, the entries written and sorted in place
+        # offsets written and read, the entries written and sorted in place, the
+        # node rows of both ends written
         a_bytes = (n_nodes * w + n_edges * (2 * w + 1) + 2 * n_edges * 4 * 3
-                   + (2 * n_nodes + 1) * 8 * 2 + 2 * n_edges * 5 * 2)
+                   + (2 * n_nodes + 1) * 8 * 2 + 2 * n_edges * 5 * 2 + 2 * n_edges * 4)
         adjacency = {"ms": round(a_ms, 4), "bytes": a_bytes,
                      "achieved_GBs": round(a_bytes / (a_ms / 1e3) / 1e9, 1)}
         log(f"adjacency: {adjacency}")
-        del a, g
+        c = api.compact(g, a, 3)  # warm-up, outputs reused below
+        cw = c.workspace
+        c_ms, _ = timed(lambda: api.compact_async(g, a, 3, stream, out=c._full, workspace=cw))
+        clen = c.chain_len.to(torch.int64)
+        compaction = {"ms": round(c_ms, 4), "min_nodes": 3, "chains": c.n_chains,
+                      "merged_chains": int((clen >= 3).sum()),
+                      "nodes_in_merged_chains": int(clen[clen >= 3].sum()),
+                      "kept_edges": c.n_kept, "cycles": c.n_cyclic,
+                      "longest_chain": int(clen.max()) if c.n_chains else 0,
+                      "nodes_per_s": round(n_nodes / (c_ms / 1e3))}
+        log(f"compaction: {compaction}")
+        del a, c, g, cw
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -497,6 +514,7 @@ def main():
         "sort_reduce_ms": round(sr_ms, 4),
         "build_as_lsd_d8": build_lsd,
         "adjacency": adjacency,
+        "compaction": compaction,
         "tuning": tuning if tuning is not None else api.get_tuning(),
         "h2d_upload_and_pack_s": round(h2d_s, 4),
     }

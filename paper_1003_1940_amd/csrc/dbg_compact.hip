@@ -16,10 +16,14 @@
 // so every state has at most one successor and one predecessor: lists and
 // cycles, each with a twin that runs the other way.
 //
-// List ranking (Wyllie's pointer jumping): every state holds one 64-bit word
-// (pointer, done, rank).  A round replaces a pending state's pointer by its
-// target's pointer and adds the target's rank; a state whose target is a head,
-// or has already found its head, is done.  States are updated in place: a
+// List ranking: every state holds one 64-bit word (pointer, done, rank).  First
+// every list head walks its list and ranks its first CMP_WALK states directly
+// (one read and one write per state; most chains of a read set's graph are
+// short).  The states left -- deeper in long lists, or on cycles -- are ranked
+// by Wyllie's pointer jumping, which continues from the walked states: a round
+// replaces a pending state's pointer by its target's pointer and adds the
+// target's rank; a state whose target is a head, or has already found its head,
+// is done.  States are updated in place: a
 // target word read while it changes is still a valid (state, distance) pair, so
 // a round only ever jumps further.  Pending states are kept on a worklist that
 // shrinks every round.  After ceil(log2(2n)) + 1 rounds every list state is done
@@ -44,6 +48,7 @@ constexpr uint32_t CMP_NIL = 0xffffffffu;
 constexpr uint64_t CMP_TILE = (uint64_t)CMP_NT * 16;
 constexpr unsigned CMP_ROUND_GRID = 2048;
 constexpr int CMP_MAX_COUNTERS = 112;
+constexpr uint32_t CMP_WALK = 256;  // list states a head's walk ranks before jumping takes over
 
 __device__ __forceinline__ void cmp_status(dbg_compact_result_t *res, uint32_t code) {
   atomicCAS(&res->status, 0u, code);
@@ -64,16 +69,27 @@ __device__ __forceinline__ void store_relaxed(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Appends `x` for every lane with `keep` set: one atomic per wave.
-__device__ __forceinline__ void wave_append(bool keep, uint32_t x, uint32_t *list,
-                                            uint32_t *count) {
+// Appends `x` for every thread with `keep` set: one atomic per workgroup.  Every
+// thread of the workgroup must call it (it holds barriers).
+__device__ __forceinline__ void block_append(bool keep, uint32_t x, uint32_t *list,
+                                             uint32_t *count, uint32_t *lds) {
+  constexpr int NW = CMP_NT / 64;
   const uint64_t bal = __ballot(keep);
-  if (!bal) return;
-  const int leader = __ffsll((long long)bal) - 1;
-  uint32_t base = 0;
-  if ((int)lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(bal));
-  base = __shfl(base, leader, 64);
-  if (keep) list[base + __popcll(bal & lanemask_lt())] = x;
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 0) lds[w] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t c = lds[i];
+      lds[i] = tot;
+      tot += c;
+    }
+    lds[NW] = tot ? atomicAdd(count, tot) : 0u;
+  }
+  __syncthreads();
+  if (keep) list[lds[NW] + lds[w] + __popcll(bal & lanemask_lt())] = x;
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(CMP_NT) void k_cmp_init(uint32_t *counters, uint32_t *cycmin,
@@ -124,22 +140,45 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_links(const uint64_t *off, uint6
   }
 }
 
-// Every state starts pointing at its predecessor; heads are done at once, the
-// others go on the first worklist.
+// Every state starts pointing at its predecessor; heads are done at once.
 __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_init(const uint32_t *link, uint64_t n,
-                                                          uint64_t *word, uint32_t *list,
-                                                          uint32_t *count) {
+                                                          uint64_t *word) {
+  const uint64_t ns = 2 * n;
+  for (uint64_t x = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; x < ns;
+       x += (uint64_t)gridDim.x * CMP_NT) {
+    const uint32_t p = link[x ^ 1u];
+    word[x] = p != CMP_NIL ? jword(p, 0u, 1u) : jword(CMP_NIL, 1u, 0u);
+  }
+}
+
+// Every list head walks its list, ranking the first CMP_WALK states directly
+// (each state of a list is reached by one walk, once).  Longer lists and cycles
+// are left to pointer jumping, which continues from the ranked states.
+__global__ __launch_bounds__(CMP_NT) void k_cmp_walk(const uint32_t *link, uint64_t n,
+                                                     uint64_t *word) {
+  const uint64_t ns = 2 * n;
+  for (uint64_t h = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; h < ns;
+       h += (uint64_t)gridDim.x * CMP_NT) {
+    if (link[h ^ 1u] != CMP_NIL) continue;  // not a head
+    uint32_t b = link[h];                    // bucket entered by the successor
+    for (uint32_t r = 1; b != CMP_NIL && r < CMP_WALK; ++r) {
+      const uint32_t x = b ^ 1u;  // the state that enters by that bucket's side
+      word[x] = jword((uint32_t)h, 1u, r);
+      b = link[x];
+    }
+  }
+}
+
+// States not ranked by a walk go on the first worklist.
+__global__ __launch_bounds__(CMP_NT) void k_cmp_pending(const uint64_t *word, uint64_t n,
+                                                        uint32_t *list, uint32_t *count) {
+  __shared__ uint32_t lds[CMP_NT / 64 + 1];
   const uint64_t ns = 2 * n;
   for (uint64_t base = blockIdx.x * (uint64_t)CMP_NT; base < ns;
        base += (uint64_t)gridDim.x * CMP_NT) {
     const uint64_t x = base + threadIdx.x;
-    bool keep = false;
-    if (x < ns) {
-      const uint32_t p = link[x ^ 1u];
-      keep = p != CMP_NIL;
-      word[x] = keep ? jword(p, 0u, 1u) : jword(CMP_NIL, 1u, 0u);
-    }
-    wave_append(keep, (uint32_t)x, list, count);
+    const bool keep = x < ns && !jdone(word[x]);
+    block_append(keep, (uint32_t)x, list, count, lds);
   }
 }
 
@@ -150,6 +189,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
                                                            uint32_t *out, uint32_t *out_count,
                                                            uint64_t *word, uint64_t ns,
                                                            dbg_compact_result_t *res) {
+  __shared__ uint32_t lds[CMP_NT / 64 + 1];
   const uint64_t c = *in_count;
   const uint64_t stride = (uint64_t)gridDim.x * CMP_NT;
   for (uint64_t base = blockIdx.x * (uint64_t)CMP_NT; base < c; base += stride) {
@@ -176,7 +216,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
         store_relaxed(&word[x], nw);
       }
     }
-    wave_append(keep, x, out, out_count);
+    block_append(keep, x, out, out_count, lds);
   }
 }
 
@@ -222,6 +262,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
                                                           uint64_t *word, uint32_t *cycmin,
                                                           uint32_t *out, uint32_t *out_count,
                                                           dbg_compact_result_t *res) {
+  __shared__ uint32_t lds[CMP_NT / 64 + 1];
   const uint64_t c = *count;
   for (uint64_t base = blockIdx.x * (uint64_t)CMP_NT; base < c;
        base += (uint64_t)gridDim.x * CMP_NT) {
@@ -247,7 +288,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
         }
       }
     }
-    wave_append(keep, x, out, out_count);
+    block_append(keep, x, out, out_count, lds);
   }
 }
 
@@ -616,7 +657,11 @@ static hipError_t run_compact(const void *node_kmer, uint64_t n, const uint8_t *
   hipLaunchKernelGGL(k_cmp_links, dim3(cmp_grid(2 * n, 16384)), dim3(CMP_NT), 0, st, off, n,
                      inc_edge, inc_end, edge_node, orient, m, link, res);
   hipLaunchKernelGGL(k_cmp_rank_init, dim3(cmp_grid(2 * n, 16384)), dim3(CMP_NT), 0, st, link,
-                     n, word, list[0], &cnt[0]);
+                     n, word);
+  hipLaunchKernelGGL(k_cmp_walk, dim3(cmp_grid(2 * n, 16384)), dim3(CMP_NT), 0, st, link, n,
+                     word);
+  hipLaunchKernelGGL(k_cmp_pending, dim3(cmp_grid(2 * n, 8192)), dim3(CMP_NT), 0, st, word, n,
+                     list[0], &cnt[0]);
   // lists: rounds 0 .. R-1 move states from list[r & 1] (count cnt[r]) to
   // list[(r + 1) & 1] (count cnt[r + 1])
   for (int r = 0; r < R; ++r)
