@@ -466,8 +466,8 @@ def main():
                 ts.append(e0.elapsed_time(e1))
             return float(np.median(ts)), r
 
-        a = api.adjacency(g, edge_nodes=True)  # warm-up (and workspace sizing)
-        a_ms, a = timed(lambda: api.adjacency_async(g, stream, edge_nodes=True))
+        a = api.adjacency(g, edge_buckets=True)  # warm-up (and workspace sizing)
+        a_ms, a = timed(lambda: api.adjacency_async(g, stream, edge_buckets=True))
         # node keys read once (index build), each edge's endpoints and orientation
         # read, the two bucket ids written, counted, read back and placed, the
         # offsets written and read, the entries written and sorted in place, the

@@ -229,8 +229,9 @@ int dbg_get_tuning(dbg_tuning_t *tuning);
  *             offsets[b] .. offsets[b + 1] - 1;
  *   inc_edge  device, 2 n_edges uint32_t: edge row of each entry;
  *   inc_end   device, 2 n_edges bytes: 0 for the u end, 1 for the v end;
- *   edge_node device, 2 n_edges uint32_t, or NULL: node rows of the u end and
- *             the v end of every edge (edge_node[2 j], edge_node[2 j + 1]).
+ *   edge_bucket device, 2 n_edges uint32_t, or NULL: the buckets of the u end
+ *             and the v end of every edge (edge_bucket[2 j], edge_bucket[2 j + 1];
+ *             node row = bucket >> 1, side = bucket & 1).
  * Inputs are a build's tables (device): node_kmer (n_nodes keys, ascending),
  * edge_u / edge_v / edge_orient (n_edges rows), key width as in dbg_build; the
  * counts are the build's n_nodes / n_edges (read from its result record).
@@ -242,7 +243,7 @@ int dbg_get_tuning(dbg_tuning_t *tuning);
 size_t dbg_adjacency_workspace_bytes(uint64_t n_nodes, uint64_t n_edges, int k);
 int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
                   const void *edge_v, const uint8_t *edge_orient, uint64_t n_edges, int k,
-                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, uint32_t *edge_node,
+                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, uint32_t *edge_bucket,
                   dbg_result_t *result, void *workspace, size_t workspace_bytes,
                   hipStream_t stream);
 
@@ -277,9 +278,9 @@ int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
  *                          on side s of a node with orientation t lies on side
  *                          s xor t of its chain; o1 = side at u, o2 = 1 - side
  *                          at v, as in the input edges).
- * Inputs (device): the build's node_kmer (ascending) and edge_orient with their
- * true counts, and dbg_adjacency's offsets, inc_edge, inc_end and edge_node of
- * the same graph.  result (device) receives n_chains, n_kept, label_len,
+ * Inputs (device): the build's node_kmer (ascending) with the true node and edge
+ * counts, and dbg_adjacency's offsets, inc_edge, inc_end and edge_bucket of the
+ * same graph (the edge sides come from the buckets).  result (device) receives n_chains, n_kept, label_len,
  * n_cyclic (cycles broken, before min_nodes) and status: DBG_OK, DBG_E_ARG (an
  * input row out of range), DBG_E_CAPACITY (labels longer than label_capacity:
  * no label byte written) or DBG_E_INTERNAL (ranking did not finish: a bug).
@@ -312,9 +313,9 @@ typedef struct {
 } dbg_compact_result_t;
 
 size_t dbg_compact_workspace_bytes(uint64_t n_nodes, uint64_t n_edges);
-int dbg_compact(const void *node_kmer, uint64_t n_nodes, const uint8_t *edge_orient,
-                uint64_t n_edges, int k, const uint64_t *adj_offsets, const uint32_t *inc_edge,
-                const uint8_t *inc_end, const uint32_t *edge_node, uint32_t min_nodes,
+int dbg_compact(const void *node_kmer, uint64_t n_nodes, uint64_t n_edges, int k,
+                const uint64_t *adj_offsets, const uint32_t *inc_edge, const uint8_t *inc_end,
+                const uint32_t *edge_bucket, uint32_t min_nodes,
                 const dbg_chains_t *out, dbg_compact_result_t *result, void *workspace,
                 size_t workspace_bytes, hipStream_t stream);
 

@@ -95,7 +95,7 @@ def load():
         lib.dbg_compact_workspace_bytes.restype = sz
         lib.dbg_compact_workspace_bytes.argtypes = [u64, u64]
         lib.dbg_compact.restype = i32
-        lib.dbg_compact.argtypes = [vp, u64, vp, u64, i32, vp, vp, vp, vp, ctypes.c_uint32,
+        lib.dbg_compact.argtypes = [vp, u64, u64, i32, vp, vp, vp, vp, ctypes.c_uint32,
                                     ctypes.POINTER(_Chains), vp, vp, sz, vp]
         lib.dbg_strerror.restype = ctypes.c_char_p
         lib.dbg_strerror.argtypes = [i32]
@@ -427,11 +427,11 @@ class Adjacency:
     """STEP-4 adjacency lists as a CSR over buckets b = 2 * node + side (side 0:
     left by a walk reading the canonical k-mer forward, side 1: entered by it):
     entries offsets[b] .. offsets[b+1] of (edge row, end), end 0 = the u end.
-    ``edge_node`` holds the node rows of both ends of every edge."""
+    ``edge_bucket`` holds the buckets of both ends of every edge."""
     offsets: torch.Tensor    # int64, 2 n_nodes + 1
     inc_edge: torch.Tensor   # int32 holding uint32 edge rows, 2 n_edges
     inc_end: torch.Tensor    # uint8, 2 n_edges
-    edge_node: torch.Tensor | None = None  # int32 holding uint32 node rows, 2 n_edges
+    edge_bucket: torch.Tensor | None = None  # int32 holding uint32 buckets, 2 n_edges
 
     def to_numpy(self):
         return (self.offsets.cpu().numpy().view(np.uint64),
@@ -440,16 +440,16 @@ class Adjacency:
 
 
 def adjacency_async(g: Graph, stream=None, result=None, workspace=None,
-                    edge_nodes: bool = False) -> Adjacency:
+                    edge_buckets: bool = False) -> Adjacency:
     """Enqueue the adjacency lists of a built graph (its true row counts must be
-    known on the host: ``g.n_nodes`` / ``g.n_edges``); ``edge_nodes`` also
-    returns the node rows of every edge's ends."""
+    known on the host: ``g.n_nodes`` / ``g.n_edges``); ``edge_buckets`` also
+    returns the bucket (2 * node + side) of every edge's ends."""
     n, m = int(g.n_nodes), int(g.n_edges)
     dev = g.node_kmer.device
     offsets = torch.empty(2 * n + 1, dtype=torch.int64, device=dev)
     inc_edge = torch.empty(max(1, 2 * m), dtype=torch.int32, device=dev)
     inc_end = torch.empty(max(1, 2 * m), dtype=torch.uint8, device=dev)
-    enode = torch.empty(max(1, 2 * m), dtype=torch.int32, device=dev) if edge_nodes else None
+    enode = torch.empty(max(1, 2 * m), dtype=torch.int32, device=dev) if edge_buckets else None
     lib = load()
     nbytes = int(lib.dbg_adjacency_workspace_bytes(n, m, g.k))
     if nbytes == 0:
@@ -469,9 +469,9 @@ def adjacency_async(g: Graph, stream=None, result=None, workspace=None,
     return a
 
 
-def adjacency(g: Graph, edge_nodes: bool = False) -> Adjacency:
+def adjacency(g: Graph, edge_buckets: bool = False) -> Adjacency:
     """Adjacency lists of a built graph (synchronises; raises on a device error)."""
-    a = adjacency_async(g, edge_nodes=edge_nodes)
+    a = adjacency_async(g, edge_buckets=edge_buckets)
     _, _, status = read_result(a.result)
     if status:
         raise DbgError(status, "dbg_adjacency (device)")
@@ -542,10 +542,10 @@ def alloc_chains(n: int, m: int, k: int, device="cuda", label_capacity: int | No
 def compact_async(g: Graph, adj: Adjacency, min_nodes: int = 3, stream=None, out=None,
                   workspace=None, result=None, label_capacity: int | None = None) -> Chains:
     """Enqueue the chain compaction of a built graph from its adjacency lists
-    (``adj`` must hold ``edge_node``: ``adjacency(g, edge_nodes=True)``)."""
+    (``adj`` must hold ``edge_bucket``: ``adjacency(g, edge_buckets=True)``)."""
     n, m = int(g.n_nodes), int(g.n_edges)
-    if adj.edge_node is None and m:
-        raise ValueError("the adjacency lists need edge_node (adjacency(g, edge_nodes=True))")
+    if adj.edge_bucket is None and m:
+        raise ValueError("the adjacency lists need edge_bucket (adjacency(g, edge_buckets=True))")
     dev = g.node_kmer.device
     out = out if out is not None else alloc_chains(n, m, g.k, dev, label_capacity)
     lib = load()
@@ -555,9 +555,9 @@ def compact_async(g: Graph, adj: Adjacency, min_nodes: int = 3, stream=None, out
     res = result if result is not None else torch.zeros(5, dtype=torch.int64, device=dev)
     st = _Chains(*[out[f].data_ptr() if f != "label_capacity" else out["labels"].numel()
                    for f, _ in _Chains._fields_])
-    rc = lib.dbg_compact(_ptr(g.node_kmer), n, _ptr(g.edge_orient), m, g.k, _ptr(adj.offsets),
+    rc = lib.dbg_compact(_ptr(g.node_kmer), n, m, g.k, _ptr(adj.offsets),
                          _ptr(adj.inc_edge), _ptr(adj.inc_end),
-                         _ptr(adj.edge_node) if adj.edge_node is not None else None,
+                         _ptr(adj.edge_bucket) if adj.edge_bucket is not None else None,
                          int(min_nodes), ctypes.byref(st), _ptr(res), _ptr(ws), ws.numel(),
                          _stream(stream))
     if rc:
@@ -572,5 +572,5 @@ def compact_async(g: Graph, adj: Adjacency, min_nodes: int = 3, stream=None, out
 
 def compact(g: Graph, adj: Adjacency | None = None, min_nodes: int = 3) -> Chains:
     """Chain compaction of a built graph (synchronises; raises on a device error)."""
-    adj = adj if adj is not None else adjacency(g, edge_nodes=True)
+    adj = adj if adj is not None else adjacency(g, edge_buckets=True)
     return compact_async(g, adj, min_nodes).finish()

@@ -10,8 +10,8 @@
 // STEP-1 table does in its ELSE branches.  The lists group the ends by (node,
 // side), nodes in table order and side 0 first, and order each group by edge
 // row, u end first.  As a CSR: bucket b = 2 * node + side holds entries
-// offsets[b] .. offsets[b + 1] of (edge row, end).  Optionally the node rows of
-// both ends of every edge are returned as well.
+// offsets[b] .. offsets[b + 1] of (edge row, end).  Optionally the bucket of
+// both ends of every edge (2 * node + side) is returned as well.
 //
 //   1. k_adj_index: a prefix index over the sorted node keys (first row of every
 //      B-bit key prefix), so an endpoint is found by one index read and a
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_count(const K *keys, uint64_t n,
                                                       const K *eu, const K *ev,
                                                       const uint8_t *orient, uint64_t m,
                                                       uint32_t *bucket, uint32_t *counts,
-                                                      uint32_t *edge_node, dbg_result_t *res) {
+                                                      uint32_t *edge_bucket, dbg_result_t *res) {
   for (uint64_t j = blockIdx.x * (uint64_t)ADJ_NT + threadIdx.x; j < m;
        j += (uint64_t)gridDim.x * ADJ_NT) {
     const uint32_t o = orient[j];
@@ -92,9 +92,9 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_count(const K *keys, uint64_t n,
     const uint32_t bu = (uint32_t)(2 * iu + (o >> 1)), bv = (uint32_t)(2 * iv + ((o & 1u) ^ 1u));
     bucket[2 * j] = bu;
     bucket[2 * j + 1] = bv;
-    if (edge_node) {
-      edge_node[2 * j] = (uint32_t)iu;
-      edge_node[2 * j + 1] = (uint32_t)iv;
+    if (edge_bucket) {
+      edge_bucket[2 * j] = bu;
+      edge_bucket[2 * j + 1] = bv;
     }
     atomicAdd(&counts[bu], 1u);
     atomicAdd(&counts[bv], 1u);
@@ -247,7 +247,7 @@ template <typename K>
 static hipError_t run_adjacency(const void *node_kmer, uint64_t n, const void *eu, const void *ev,
                                 const uint8_t *orient, uint64_t m, const AdjLayout &L,
                                 uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end,
-                                uint32_t *edge_node, dbg_result_t *res, char *ws,
+                                uint32_t *edge_bucket, dbg_result_t *res, char *ws,
                                 hipStream_t st) {
   const K *keys = static_cast<const K *>(node_kmer);
   uint32_t *first = reinterpret_cast<uint32_t *>(ws + L.first);
@@ -262,7 +262,7 @@ static hipError_t run_adjacency(const void *node_kmer, uint64_t n, const void *e
                      L.shift, L.nbins, first);
   hipLaunchKernelGGL(k_adj_count<K>, dim3(adj_grid(m, 16384)), dim3(ADJ_NT), 0, st, keys, n,
                      first, L.nbins, L.shift, static_cast<const K *>(eu), static_cast<const K *>(ev),
-                     orient, m, bucket, counts, edge_node, res);
+                     orient, m, bucket, counts, edge_bucket, res);
   hipLaunchKernelGGL(k_adj_scan_reduce, dim3((unsigned)nsum), dim3(ADJ_NT), 0, st, counts, nb,
                      sums);
   hipLaunchKernelGGL(k_adj_scan_sums, dim3(1), dim3(1024), 0, st, sums, nsum);
@@ -287,7 +287,7 @@ size_t dbg_adjacency_workspace_bytes(uint64_t n_nodes, uint64_t n_edges, int k) 
 
 int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
                   const void *edge_v, const uint8_t *edge_orient, uint64_t n_edges, int k,
-                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, uint32_t *edge_node,
+                  uint64_t *offsets, uint32_t *inc_edge, uint8_t *inc_end, uint32_t *edge_bucket,
                   dbg_result_t *result, void *workspace, size_t workspace_bytes,
                   hipStream_t stream) {
   if (k < 1 || k > 63 || (k & 1) == 0) return DBG_E_K;
@@ -302,11 +302,11 @@ int dbg_adjacency(const void *node_kmer, uint64_t n_nodes, const void *edge_u,
   char *ws = static_cast<char *>(workspace);
   const hipError_t e =
       k <= 31 ? dbg::run_adjacency<uint64_t>(node_kmer, n_nodes, edge_u, edge_v, edge_orient,
-                                             n_edges, L, offsets, inc_edge, inc_end, edge_node,
+                                             n_edges, L, offsets, inc_edge, inc_end, edge_bucket,
                                              result, ws, stream)
               : dbg::run_adjacency<unsigned __int128>(node_kmer, n_nodes, edge_u, edge_v,
                                                       edge_orient, n_edges, L, offsets, inc_edge,
-                                                      inc_end, edge_node, result, ws, stream);
+                                                      inc_end, edge_bucket, result, ws, stream);
   return e == hipSuccess ? DBG_OK : DBG_E_HIP;
 }
 

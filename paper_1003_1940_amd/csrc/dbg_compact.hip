@@ -1,5 +1,6 @@
 // Bi-directed chain compaction (Sec. 7): the simplified graph of a built graph,
-// from its node keys, edge orientations and STEP-4 adjacency lists.
+// from its node keys and STEP-4 adjacency lists (with the bucket of every edge
+// end).
 //
 // Sides are those of the adjacency lists: side 0 of a node is left, side 1
 // entered, by a walk reading its canonical k-mer forward.  An edge is a candidate
@@ -104,80 +105,121 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_init(uint32_t *counters, uint32_
   for (uint64_t v = t0; v < n; v += (uint64_t)gridDim.x * CMP_NT) cycmin[v] = CMP_NIL;
 }
 
-// link[b] for every bucket b = 2v + s: the bucket at the other end of the edge
-// whose end is alone on side s of v, when that end too is alone on its side and
-// the edge is not a self-loop; NIL otherwise.
+// One record per state: its link (the bucket at the other end of the candidate
+// edge on the side the state leaves by, or NIL) and its jump word, in one 16-byte
+// line, so that a walk step reads the one and writes the other in the same line.
+struct alignas(16) SRec {
+  uint32_t link;
+  uint32_t spare;
+  uint64_t word;
+};
+
+template <typename K>
+__device__ __forceinline__ K state_kmer(const K *keys, uint32_t s, int k) {
+  const K key = keys[s >> 1];
+  return (s & 1u) ? revcomp(key, k) : key;
+}
+
+// Per node v: the links of both sides s -- the bucket at the other end of the
+// edge whose end is alone on side s of v, when that end too is alone on its side
+// and the edge is not a self-loop; NIL otherwise -- and the first jump words of
+// both states (pointer = predecessor, pred(2v + t) = link of side 1 - t; heads
+// are done at once).  A node linked on one side only ends a chain: its state
+// with a successor but no predecessor heads a list and is recorded in the
+// workgroup's own segment of `heads` (nodes [blockIdx.x * chunk, ...) give at
+// most that many heads; no global atomics).
 __global__ __launch_bounds__(CMP_NT) void k_cmp_links(const uint64_t *off, uint64_t n,
                                                       const uint32_t *inc_edge,
                                                       const uint8_t *inc_end,
-                                                      const uint32_t *edge_node,
-                                                      const uint8_t *orient, uint64_t m,
-                                                      uint32_t *link, dbg_compact_result_t *res) {
-  const uint64_t nb = 2 * n;
-  for (uint64_t b = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; b < nb;
-       b += (uint64_t)gridDim.x * CMP_NT) {
-    const uint64_t s0 = off[b], s1 = off[b + 1];
-    uint32_t out = CMP_NIL;
-    if (s1 == s0 + 1 && s0 < 2 * m) {
-      const uint32_t e = inc_edge[s0];
-      const uint32_t t = inc_end[s0];
-      if (e >= m || t > 1u) {
-        cmp_status(res, DBG_E_ARG);
-      } else {
-        const uint32_t w = edge_node[2 * (uint64_t)e + (t ^ 1u)];
-        if (w >= n) {
+                                                      const uint32_t *edge_bucket, uint64_t m,
+                                                      uint64_t chunk, SRec *rec,
+                                                      uint32_t *heads, uint32_t *seg_count,
+                                                      dbg_compact_result_t *res) {
+  __shared__ uint32_t seg;
+  if (threadIdx.x == 0) seg = 0;
+  __syncthreads();
+  const uint64_t v0 = blockIdx.x * chunk;
+  const uint64_t v1 = v0 + chunk < n ? v0 + chunk : n;
+  for (uint64_t v = v0 + threadIdx.x; v < v1; v += CMP_NT) {
+    uint32_t l[2];
+    for (int s = 0; s < 2; ++s) {
+      const uint64_t b = 2 * v + s;
+      const uint64_t s0 = off[b], s1 = off[b + 1];
+      uint32_t out = CMP_NIL;
+      if (s1 == s0 + 1 && s0 < 2 * m) {
+        const uint32_t e = inc_edge[s0];
+        const uint32_t t = inc_end[s0];
+        if (e >= m || t > 1u) {
           cmp_status(res, DBG_E_ARG);
-        } else if ((uint64_t)w != (b >> 1)) {
-          const uint32_t o = orient[e];
-          // the other end: the u end lies on side o1, the v end on side 1 - o2
-          const uint32_t sw = t == 1u ? (o >> 1) & 1u : (o & 1u) ^ 1u;
-          const uint64_t bw = 2 * (uint64_t)w + sw;
-          if (off[bw + 1] == off[bw] + 1) out = (uint32_t)bw;
+        } else {
+          const uint32_t bw = edge_bucket[2 * (uint64_t)e + (t ^ 1u)];  // the other end
+          if (bw >= 2 * n) cmp_status(res, DBG_E_ARG);
+          else if ((uint64_t)(bw >> 1) != v && off[bw + 1] == off[bw] + 1) out = bw;
         }
       }
+      l[s] = out;
     }
-    link[b] = out;
+    rec[2 * v] = SRec{l[0], 0u, l[1] != CMP_NIL ? jword(l[1], 0u, 1u) : jword(CMP_NIL, 1u, 0u)};
+    rec[2 * v + 1] =
+        SRec{l[1], 0u, l[0] != CMP_NIL ? jword(l[0], 0u, 1u) : jword(CMP_NIL, 1u, 0u)};
+    if ((l[0] == CMP_NIL) != (l[1] == CMP_NIL)) {
+      const uint32_t h = (uint32_t)(2 * v) + (l[0] != CMP_NIL ? 0u : 1u);
+      heads[v0 + atomicAdd(&seg, 1u)] = h;
+    }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) seg_count[blockIdx.x] = seg;
 }
 
-// Every state starts pointing at its predecessor; heads are done at once.
-__global__ __launch_bounds__(CMP_NT) void k_cmp_rank_init(const uint32_t *link, uint64_t n,
-                                                          uint64_t *word) {
-  const uint64_t ns = 2 * n;
-  for (uint64_t x = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; x < ns;
-       x += (uint64_t)gridDim.x * CMP_NT) {
-    const uint32_t p = link[x ^ 1u];
-    word[x] = p != CMP_NIL ? jword(p, 0u, 1u) : jword(CMP_NIL, 1u, 0u);
-  }
-}
-
-// Every list head walks its list, ranking the first CMP_WALK states directly
+// Every list head walks its list, ranking its first CMP_WALK states directly
 // (each state of a list is reached by one walk, once).  Longer lists and cycles
-// are left to pointer jumping, which continues from the ranked states.
-__global__ __launch_bounds__(CMP_NT) void k_cmp_walk(const uint32_t *link, uint64_t n,
-                                                     uint64_t *word) {
-  const uint64_t ns = 2 * n;
-  for (uint64_t h = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; h < ns;
-       h += (uint64_t)gridDim.x * CMP_NT) {
-    if (link[h ^ 1u] != CMP_NIL) continue;  // not a head
-    uint32_t b = link[h];                    // bucket entered by the successor
-    for (uint32_t r = 1; b != CMP_NIL && r < CMP_WALK; ++r) {
-      const uint32_t x = b ^ 1u;  // the state that enters by that bucket's side
-      word[x] = jword((uint32_t)h, 1u, r);
-      b = link[x];
+// are left to pointer jumping, which continues from the ranked states.  A walk
+// that reaches the end of its list knows both heads of the chain (its own and
+// the twin's, the state after the tail's twin); it records in its head's rank
+// field whether its copy is the canonical one (1) or not (2); 0 stays for lists
+// too long to walk.  Each lane takes a new head from its workgroup's segment as
+// soon as its walk ends (one flat loop, so lanes do not wait for each other).
+template <typename K>
+__global__ __launch_bounds__(CMP_NT) void k_cmp_walk(SRec *rec, const uint32_t *heads,
+                                                     const uint32_t *seg_count, uint64_t chunk,
+                                                     const K *keys, int k) {
+  __shared__ uint32_t next;
+  if (threadIdx.x == 0) next = 0;
+  __syncthreads();
+  const uint32_t c = seg_count[blockIdx.x];
+  const uint32_t *seg = heads + blockIdx.x * chunk;
+  uint32_t h = CMP_NIL, b = CMP_NIL, last = 0, r = 0;
+  while (true) {
+    if (b == CMP_NIL || r >= CMP_WALK) {
+      if (h != CMP_NIL && b == CMP_NIL) {  // the walk reached the tail `last`
+        const K a = state_kmer(keys, h, k), z = state_kmer(keys, last ^ 1u, k);
+        rec[h].word = jword(CMP_NIL, 1u, a < z ? 1u : 2u);
+      }
+      const uint32_t j = atomicAdd(&next, 1u);
+      if (j >= c) break;
+      h = seg[j];
+      b = rec[h].link;  // bucket entered by the successor
+      last = h;
+      r = 1;
+      continue;
     }
+    const uint32_t x = b ^ 1u;  // the state that enters by that bucket's side
+    rec[x].word = jword(h, 1u, r);
+    last = x;
+    b = rec[x].link;
+    ++r;
   }
 }
 
 // States not ranked by a walk go on the first worklist.
-__global__ __launch_bounds__(CMP_NT) void k_cmp_pending(const uint64_t *word, uint64_t n,
+__global__ __launch_bounds__(CMP_NT) void k_cmp_pending(const SRec *rec, uint64_t n,
                                                         uint32_t *list, uint32_t *count) {
   __shared__ uint32_t lds[CMP_NT / 64 + 1];
   const uint64_t ns = 2 * n;
   for (uint64_t base = blockIdx.x * (uint64_t)CMP_NT; base < ns;
        base += (uint64_t)gridDim.x * CMP_NT) {
     const uint64_t x = base + threadIdx.x;
-    const bool keep = x < ns && !jdone(word[x]);
+    const bool keep = x < ns && !jdone(rec[x].word);
     block_append(keep, (uint32_t)x, list, count, lds);
   }
 }
@@ -187,7 +229,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_pending(const uint64_t *word, ui
 __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
                                                            const uint32_t *in_count,
                                                            uint32_t *out, uint32_t *out_count,
-                                                           uint64_t *word, uint64_t ns,
+                                                           SRec *rec, uint64_t ns,
                                                            dbg_compact_result_t *res) {
   __shared__ uint32_t lds[CMP_NT / 64 + 1];
   const uint64_t c = *in_count;
@@ -198,12 +240,12 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
     uint32_t x = 0;
     if (i < c) {
       x = in[i];
-      const uint64_t w = word[x];  // only this thread writes word[x]
+      const uint64_t w = rec[x].word;  // only this thread writes it
       const uint32_t y = jptr(w);
       if (y >= ns) {  // a pending state always points at a state
         cmp_status(res, DBG_E_INTERNAL);
       } else {
-        const uint64_t wy = load_relaxed(&word[y]);
+        const uint64_t wy = load_relaxed(&rec[y].word);
         uint64_t r = (uint64_t)jrank(w) + jrank(wy);
         if (r > 0x7fffffffull) r = 0x7fffffffull;  // only on cycles, re-ranked later
         uint64_t nw;
@@ -213,7 +255,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
           nw = jword(jptr(wy), 0u, (uint32_t)r);
           keep = true;
         }
-        store_relaxed(&word[x], nw);
+        store_relaxed(&rec[x].word, nw);
       }
     }
     block_append(keep, x, out, out_count, lds);
@@ -222,44 +264,42 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
 
 // Cycle states: word = (predecessor, smallest node seen so far).
 __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_init(const uint32_t *list,
-                                                         const uint32_t *count,
-                                                         const uint32_t *link, uint64_t *word) {
+                                                         const uint32_t *count, SRec *rec) {
   const uint64_t c = *count;
   for (uint64_t i = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; i < c;
        i += (uint64_t)gridDim.x * CMP_NT) {
     const uint32_t x = list[i];
-    const uint32_t p = link[x ^ 1u];  // NIL only after a bug; k_cmp_cyc_round flags it
+    const uint32_t p = rec[x ^ 1u].link;  // NIL only after a bug; k_cmp_cyc_round flags it
     const uint32_t lo = (x >> 1) < (p >> 1) ? (x >> 1) : (p >> 1);
-    word[x] = ((uint64_t)p << 32) | lo;
+    rec[x].word = ((uint64_t)p << 32) | lo;
   }
 }
 
 __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_round(const uint32_t *list,
-                                                          const uint32_t *count,
-                                                          uint64_t *word, uint64_t ns,
+                                                          const uint32_t *count, SRec *rec,
+                                                          uint64_t ns,
                                                           dbg_compact_result_t *res) {
   const uint64_t c = *count;
   for (uint64_t i = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; i < c;
        i += (uint64_t)gridDim.x * CMP_NT) {
     const uint32_t x = list[i];
-    const uint64_t w = word[x];
+    const uint64_t w = rec[x].word;
     const uint32_t y = (uint32_t)(w >> 32);
     if (y >= ns) {  // cycle states point at cycle states
       cmp_status(res, DBG_E_INTERNAL);
       continue;
     }
-    const uint64_t wy = load_relaxed(&word[y]);
+    const uint64_t wy = load_relaxed(&rec[y].word);
     const uint32_t a = (uint32_t)w, b = (uint32_t)wy;
-    store_relaxed(&word[x], (wy & 0xffffffff00000000ull) | (a < b ? a : b));
+    store_relaxed(&rec[x].word, (wy & 0xffffffff00000000ull) | (a < b ? a : b));
   }
 }
 
 // Break every cycle at its smallest node v: v+ heads the cycle through it, and
 // the state after v- heads the twin.  Node v's smallest cycle node is recorded.
 __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
-                                                          const uint32_t *count,
-                                                          const uint32_t *link, uint64_t n,
-                                                          uint64_t *word, uint32_t *cycmin,
+                                                          const uint32_t *count, SRec *rec,
+                                                          uint64_t n, uint32_t *cycmin,
                                                           uint32_t *out, uint32_t *out_count,
                                                           dbg_compact_result_t *res) {
   __shared__ uint32_t lds[CMP_NT / 64 + 1];
@@ -271,19 +311,19 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
     uint32_t x = 0;
     if (i < c) {
       x = list[i];
-      const uint32_t lo = (uint32_t)word[x];
-      const uint32_t l1 = lo < n ? link[2 * (uint64_t)lo + 1] : CMP_NIL;
+      const uint32_t lo = (uint32_t)rec[x].word;
+      const uint32_t l1 = lo < n ? rec[2 * (uint64_t)lo + 1].link : CMP_NIL;
       if (l1 == CMP_NIL) {  // the smallest node of a cycle is linked on both sides
         cmp_status(res, DBG_E_INTERNAL);
-        word[x] = jword(CMP_NIL, 1u, 0u);
+        rec[x].word = jword(CMP_NIL, 1u, 0u);
       } else {
         if ((x & 1u) == 0) cycmin[x >> 1] = lo;
         const uint32_t h1 = 2 * lo, h2 = l1 ^ 1u;
         if (x == h1 || x == h2) {
-          word[x] = jword(CMP_NIL, 1u, 0u);
+          rec[x].word = jword(CMP_NIL, 1u, 0u);
           if (x == h1) atomicAdd((unsigned long long *)&res->n_cyclic, 1ull);
         } else {
-          word[x] = jword(link[x ^ 1u], 0u, 1u);
+          rec[x].word = jword(rec[x ^ 1u].link, 0u, 1u);
           keep = true;
         }
       }
@@ -292,27 +332,28 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
   }
 }
 
-template <typename K>
-__device__ __forceinline__ K state_kmer(const K *keys, uint32_t s, int k) {
-  const K key = keys[s >> 1];
-  return (s & 1u) ? revcomp(key, k) : key;
-}
-
 // Per node: its chain's first node, its rank and orientation along the chain's
-// canonical walk, and its chain's length with bit 31 = cyclic.
+// canonical walk, and its chain's length with bit 31 = cyclic.  The node also
+// marks the edges merged into its chain (keep = 0): the candidate edge on each
+// linked side, written by the edge's u end only, except the edge that closed a
+// broken cycle (the one leaving the chain's last node and entering its first).
 template <typename K>
 __global__ __launch_bounds__(CMP_NT) void k_cmp_nodes(const K *keys, uint64_t n, int k,
-                                                      uint32_t min_nodes, const uint64_t *word,
+                                                      uint32_t min_nodes, const SRec *rec,
                                                       const uint32_t *cycmin,
+                                                      const uint64_t *off,
+                                                      const uint32_t *inc_edge,
+                                                      const uint8_t *inc_end, uint64_t m,
                                                       uint32_t *node_rank, uint8_t *node_orient,
                                                       uint32_t *head, uint32_t *lenc,
-                                                      const uint32_t *final_count,
+                                                      uint8_t *keep, const uint32_t *final_count,
                                                       dbg_compact_result_t *res) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && *final_count != 0u)
     cmp_status(res, DBG_E_INTERNAL);
   for (uint64_t v = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; v < n;
        v += (uint64_t)gridDim.x * CMP_NT) {
-    const uint64_t w0 = word[2 * v], w1 = word[2 * v + 1];
+    const SRec s0 = rec[2 * v], s1 = rec[2 * v + 1];
+    const uint64_t w0 = s0.word, w1 = s1.word;
     uint32_t h0 = jptr(w0) == CMP_NIL ? (uint32_t)(2 * v) : jptr(w0);
     uint32_t h1 = jptr(w1) == CMP_NIL ? (uint32_t)(2 * v + 1) : jptr(w1);
     if (h0 >= 2 * n || h1 >= 2 * n) {  // only after a failed ranking
@@ -320,7 +361,9 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_nodes(const K *keys, uint64_t n,
       h0 = (uint32_t)(2 * v);
       h1 = (uint32_t)(2 * v + 1);
     }
-    const uint32_t r0 = jrank(w0), r1 = jrank(w1);
+    // a head's rank field holds its walk's verdict, not a rank
+    const uint32_t r0 = jptr(w0) == CMP_NIL ? 0u : jrank(w0);
+    const uint32_t r1 = jptr(w1) == CMP_NIL ? 0u : jrank(w1);
     uint32_t len = r0 + r1 + 1, rank = 0, o = 0, hd = (uint32_t)v, cyc = 0;
     if (len > 1) {
       const uint32_t lo = cycmin[v];
@@ -329,7 +372,9 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_nodes(const K *keys, uint64_t n,
         first = h0 == 2 * lo;
         cyc = 1;
       } else {
-        first = state_kmer(keys, h0, k) < state_kmer(keys, h1, k);
+        const uint32_t verdict = jrank(rec[h0].word) & 3u;
+        first = verdict == 1u ||
+                (verdict == 0u && state_kmer(keys, h0, k) < state_kmer(keys, h1, k));
       }
       o = first ? 0u : 1u;
       rank = first ? r0 : r1;
@@ -344,6 +389,19 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_nodes(const K *keys, uint64_t n,
     node_orient[v] = (uint8_t)o;
     head[v] = hd;
     lenc[v] = len | (cyc << 31);
+    if (len > 1) {
+      const uint32_t links[2] = {s0.link, s1.link};
+      for (uint32_t s = 0; s < 2; ++s) {
+        if (links[s] == CMP_NIL) continue;
+        const uint64_t at = off[2 * v + s];
+        if (at >= 2 * m) continue;
+        const uint32_t e = inc_edge[at];
+        if (inc_end[at] != 0 || e >= m) continue;  // the v end leaves it to the u end
+        const uint32_t ws = s ^ o;  // 0: the side the walk leaves by, 1: enters by
+        const bool closing = cyc && ((rank == 0 && ws == 1u) || (rank == len - 1 && ws == 0u));
+        if (!closing) keep[e] = 0;
+      }
+    }
   }
 }
 
@@ -441,7 +499,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_scan_apply(Src src, uint64_t n,
 // First nodes: number their chains and fill the chain table.
 struct ChainSink {
   const uint32_t *lenc;
-  uint32_t *chain_of_head;
+  uint64_t *head_info;  // per first node: label offset, chain number
   uint32_t *chain_head;
   uint32_t *chain_len;
   uint8_t *chain_cyclic;
@@ -449,7 +507,8 @@ struct ChainSink {
   __device__ void operator()(uint64_t v, uint64_t a, uint64_t b, uint64_t is_first) const {
     if (!is_first) return;
     const uint32_t lc = lenc[v];
-    chain_of_head[v] = (uint32_t)a;
+    head_info[2 * v] = b;
+    head_info[2 * v + 1] = a;
     chain_head[a] = (uint32_t)v;
     chain_len[a] = lc & 0x7fffffffu;
     chain_cyclic[a] = (uint8_t)(lc >> 31);
@@ -477,10 +536,9 @@ __global__ void k_cmp_chain_totals(const uint64_t *totals, uint64_t *label_off,
 template <typename K>
 __global__ __launch_bounds__(CMP_NT) void k_cmp_labels(const K *keys, uint64_t n, int k,
                                                        const uint32_t *head,
-                                                       const uint32_t *chain_of_head,
+                                                       const uint64_t *head_info,
                                                        const uint32_t *node_rank,
                                                        const uint8_t *node_orient,
-                                                       const uint64_t *label_off,
                                                        uint64_t label_cap,
                                                        uint32_t *node_chain, uint8_t *labels,
                                                        dbg_compact_result_t *res) {
@@ -489,17 +547,19 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_labels(const K *keys, uint64_t n
   for (uint64_t v = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; v < n;
        v += (uint64_t)gridDim.x * CMP_NT) {
     const uint32_t hd = head[v];
-    const uint32_t c = hd < n ? chain_of_head[hd] : CMP_NIL;
+    ulonglong2 hi = make_ulonglong2(0, CMP_NIL);
+    if (hd < n) hi = reinterpret_cast<const ulonglong2 *>(head_info)[hd];
+    const uint64_t c = hi.y;
     if (c >= n_chains) {  // every chain's first node was numbered
       cmp_status(res, DBG_E_INTERNAL);
       node_chain[v] = CMP_NIL;
       continue;
     }
-    node_chain[v] = c;
+    node_chain[v] = (uint32_t)c;
     if (!write) continue;
     const uint32_t r = node_rank[v];
     const K s = state_kmer(keys, (uint32_t)(2 * v + node_orient[v]), k);
-    const uint64_t at = label_off[c];
+    const uint64_t at = hi.x;
     if (at + (uint64_t)(k - 1) + r >= label_cap) {
       cmp_status(res, DBG_E_INTERNAL);
       continue;
@@ -514,48 +574,14 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_labels(const K *keys, uint64_t n
   }
 }
 
-// Per edge: kept (1) unless it joins two consecutive nodes of a chain (a
-// candidate edge inside a chain of two or more nodes, other than the edge that
-// closed a broken cycle: the one entering the chain's first node).
-__global__ __launch_bounds__(CMP_NT) void k_cmp_edges(const uint32_t *edge_node,
-                                                      const uint8_t *orient, uint64_t m,
-                                                      uint64_t n, const uint64_t *off,
-                                                      const uint32_t *node_rank,
-                                                      const uint8_t *node_orient,
-                                                      const uint32_t *lenc, uint8_t *keep,
-                                                      dbg_compact_result_t *res) {
-  for (uint64_t e = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; e < m;
-       e += (uint64_t)gridDim.x * CMP_NT) {
-    const uint32_t u = edge_node[2 * e], v = edge_node[2 * e + 1];
-    if (u >= n || v >= n) {
-      cmp_status(res, DBG_E_ARG);
-      keep[e] = 1;
-      continue;
-    }
-    const uint32_t o = orient[e];
-    const uint32_t su = (o >> 1) & 1u, sv = (o & 1u) ^ 1u;
-    const uint64_t bu = 2 * (uint64_t)u + su, bv = 2 * (uint64_t)v + sv;
-    const bool cand = u != v && off[bu + 1] == off[bu] + 1 && off[bv + 1] == off[bv] + 1;
-    bool merged = false;
-    if (cand) {
-      const uint32_t lc = lenc[u];  // every node holds its chain's length
-      if ((lc & 0x7fffffffu) > 1u) {
-        merged = true;
-        if (lc >> 31) {
-          // closing edge of a broken cycle: its end at the first node lies on the
-          // side the chain's walk enters that node by
-          if (node_rank[u] == 0 && (su ^ node_orient[u]) == 1u) merged = false;
-          if (node_rank[v] == 0 && (sv ^ node_orient[v]) == 1u) merged = false;
-        }
-      }
-    }
-    keep[e] = merged ? 0 : 1;
-  }
+__global__ __launch_bounds__(CMP_NT) void k_cmp_fill_u8(uint8_t *a, uint64_t n, uint8_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * CMP_NT)
+    a[i] = v;
 }
 
 struct KeptSink {
-  const uint32_t *edge_node;
-  const uint8_t *orient;
+  const uint32_t *edge_bucket;
   const uint32_t *node_chain;
   const uint8_t *node_orient;
   uint64_t n;
@@ -565,11 +591,13 @@ struct KeptSink {
   uint8_t *kept_orient;
   __device__ void operator()(uint64_t e, uint64_t a, uint64_t, uint64_t is_kept) const {
     if (!is_kept) return;
-    const uint32_t u = edge_node[2 * e], v = edge_node[2 * e + 1];
-    if (u >= n || v >= n) return;
-    const uint32_t o = orient[e];
-    const uint32_t cu = ((o >> 1) & 1u) ^ node_orient[u];
-    const uint32_t cv = ((o & 1u) ^ 1u) ^ node_orient[v];
+    const uint32_t bu = edge_bucket[2 * e], bv = edge_bucket[2 * e + 1];
+    if (bu >= 2 * n || bv >= 2 * n) return;
+    const uint32_t u = bu >> 1, v = bv >> 1;
+    // an end on side s of a node read with orientation t lies on side s xor t of
+    // its chain; o1 = side at u, o2 = 1 - side at v
+    const uint32_t cu = (bu & 1u) ^ node_orient[u];
+    const uint32_t cv = (bv & 1u) ^ node_orient[v];
     kept_row[a] = (uint32_t)e;  // a < number of kept edges <= m
     kept_u[a] = node_chain[u];
     kept_v[a] = node_chain[v];
@@ -591,10 +619,10 @@ static inline unsigned cmp_grid(uint64_t n, uint64_t cap) {
 static inline size_t cmp_align(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct CmpLayout {
-  size_t link, word, list0, list1, counters, cycmin, head, lenc, chain_of_head, keep, sums,
-      totals, total;
+  size_t rec, list0, list1, counters, cycmin, head, lenc, head_info, keep, sums, totals,
+      heads, seg_count, total;
   int rounds;
-  uint64_t tiles;
+  uint64_t tiles, chunk, segments;
 };
 
 static CmpLayout cmp_layout(uint64_t n, uint64_t m) {
@@ -605,21 +633,27 @@ static CmpLayout cmp_layout(uint64_t n, uint64_t m) {
   L.rounds = r + 1;
   const uint64_t big = n > m ? n : m;
   L.tiles = big / CMP_TILE + 1;
+  // about 4096 workgroups collect and walk the chain ends, each over its own
+  // range of nodes
+  L.chunk = ((n + 4095) / 4096 + CMP_NT - 1) / CMP_NT * CMP_NT;
+  if (L.chunk < CMP_NT) L.chunk = CMP_NT;
+  L.segments = (n + L.chunk - 1) / L.chunk;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off = cmp_align(off + (bytes ? bytes : 1));
     return o;
   };
-  L.link = take(2 * n * sizeof(uint32_t));
-  L.word = take(2 * n * sizeof(uint64_t));
+  L.rec = take(2 * n * sizeof(SRec));
   L.list0 = take(2 * n * sizeof(uint32_t));
   L.list1 = take(2 * n * sizeof(uint32_t));
   L.counters = take(CMP_MAX_COUNTERS * sizeof(uint32_t));
   L.cycmin = take(n * sizeof(uint32_t));
   L.head = take(n * sizeof(uint32_t));
   L.lenc = take(n * sizeof(uint32_t));
-  L.chain_of_head = take(n * sizeof(uint32_t));
+  L.head_info = take(2 * n * sizeof(uint64_t));
+  L.heads = take(n * sizeof(uint32_t));
+  L.seg_count = take((L.segments + 1) * sizeof(uint32_t));
   L.keep = take(m);
   L.sums = take(2 * L.tiles * sizeof(uint64_t));
   L.totals = take(4 * sizeof(uint64_t));
@@ -628,21 +662,22 @@ static CmpLayout cmp_layout(uint64_t n, uint64_t m) {
 }
 
 template <typename K>
-static hipError_t run_compact(const void *node_kmer, uint64_t n, const uint8_t *orient,
-                              uint64_t m, int k, const uint64_t *off, const uint32_t *inc_edge,
-                              const uint8_t *inc_end, const uint32_t *edge_node,
+static hipError_t run_compact(const void *node_kmer, uint64_t n, uint64_t m, int k,
+                              const uint64_t *off, const uint32_t *inc_edge,
+                              const uint8_t *inc_end, const uint32_t *edge_bucket,
                               uint32_t min_nodes, const dbg_chains_t &o, const CmpLayout &L,
                               dbg_compact_result_t *res, char *ws, hipStream_t st) {
   const K *keys = static_cast<const K *>(node_kmer);
-  uint32_t *link = reinterpret_cast<uint32_t *>(ws + L.link);
-  uint64_t *word = reinterpret_cast<uint64_t *>(ws + L.word);
+  SRec *rec = reinterpret_cast<SRec *>(ws + L.rec);
   uint32_t *list[2] = {reinterpret_cast<uint32_t *>(ws + L.list0),
                        reinterpret_cast<uint32_t *>(ws + L.list1)};
   uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + L.counters);
   uint32_t *cycmin = reinterpret_cast<uint32_t *>(ws + L.cycmin);
   uint32_t *head = reinterpret_cast<uint32_t *>(ws + L.head);
   uint32_t *lenc = reinterpret_cast<uint32_t *>(ws + L.lenc);
-  uint32_t *chain_of_head = reinterpret_cast<uint32_t *>(ws + L.chain_of_head);
+  uint64_t *head_info = reinterpret_cast<uint64_t *>(ws + L.head_info);
+  uint32_t *heads = reinterpret_cast<uint32_t *>(ws + L.heads);
+  uint32_t *seg_count = reinterpret_cast<uint32_t *>(ws + L.seg_count);
   uint8_t *keep = reinterpret_cast<uint8_t *>(ws + L.keep);
   uint64_t *sums = reinterpret_cast<uint64_t *>(ws + L.sums);
   uint64_t *totals = reinterpret_cast<uint64_t *>(ws + L.totals);
@@ -654,59 +689,57 @@ static hipError_t run_compact(const void *node_kmer, uint64_t n, const uint8_t *
     hipLaunchKernelGGL(k_cmp_empty, dim3(1), dim3(1), 0, st, o.label_offsets);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_cmp_links, dim3(cmp_grid(2 * n, 16384)), dim3(CMP_NT), 0, st, off, n,
-                     inc_edge, inc_end, edge_node, orient, m, link, res);
-  hipLaunchKernelGGL(k_cmp_rank_init, dim3(cmp_grid(2 * n, 16384)), dim3(CMP_NT), 0, st, link,
-                     n, word);
-  hipLaunchKernelGGL(k_cmp_walk, dim3(cmp_grid(2 * n, 16384)), dim3(CMP_NT), 0, st, link, n,
-                     word);
-  hipLaunchKernelGGL(k_cmp_pending, dim3(cmp_grid(2 * n, 8192)), dim3(CMP_NT), 0, st, word, n,
+  hipLaunchKernelGGL(k_cmp_links, dim3((unsigned)L.segments), dim3(CMP_NT), 0, st, off, n,
+                     inc_edge, inc_end, edge_bucket, m, L.chunk, rec, heads, seg_count, res);
+  hipLaunchKernelGGL(k_cmp_walk<K>, dim3((unsigned)L.segments), dim3(CMP_NT), 0, st, rec, heads,
+                     seg_count, L.chunk, keys, k);
+  hipLaunchKernelGGL(k_cmp_pending, dim3(cmp_grid(2 * n, 8192)), dim3(CMP_NT), 0, st, rec, n,
                      list[0], &cnt[0]);
   // lists: rounds 0 .. R-1 move states from list[r & 1] (count cnt[r]) to
   // list[(r + 1) & 1] (count cnt[r + 1])
   for (int r = 0; r < R; ++r)
     hipLaunchKernelGGL(k_cmp_rank_round, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, list[r & 1],
-                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], word, 2 * n, res);
+                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], rec, 2 * n, res);
   // cycles: the states left in list[R & 1]
   uint32_t *cl = list[R & 1];
-  hipLaunchKernelGGL(k_cmp_cyc_init, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R], link,
-                     word);
+  hipLaunchKernelGGL(k_cmp_cyc_init, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R], rec);
   for (int r = 0; r < R; ++r)
     hipLaunchKernelGGL(k_cmp_cyc_round, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R],
-                       word, 2 * n, res);
+                       rec, 2 * n, res);
   hipLaunchKernelGGL(k_cmp_cyc_break, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R],
-                     link, n, word, cycmin, list[(R + 1) & 1], &cnt[R + 1], res);
+                     rec, n, cycmin, list[(R + 1) & 1], &cnt[R + 1], res);
   for (int r = R + 1; r <= 2 * R; ++r)
     hipLaunchKernelGGL(k_cmp_rank_round, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, list[r & 1],
-                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], word, 2 * n, res);
+                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], rec, 2 * n, res);
+  if (m)
+    hipLaunchKernelGGL(k_cmp_fill_u8, dim3(cmp_grid(m, 8192)), dim3(CMP_NT), 0, st, keep, m,
+                       (uint8_t)1);
   hipLaunchKernelGGL(k_cmp_nodes<K>, dim3(cmp_grid(n, 16384)), dim3(CMP_NT), 0, st, keys, n, k,
-                     min_nodes, word, cycmin, o.node_rank, o.node_orient, head, lenc,
-                     &cnt[2 * R + 1], res);
+                     min_nodes, rec, cycmin, off, inc_edge, inc_end, m, o.node_rank,
+                     o.node_orient, head, lenc, keep, &cnt[2 * R + 1], res);
   // chains in the order of their first node; label offsets
   const uint64_t nt_nodes = n / CMP_TILE + 1;
   const NodeSrc ns{head, lenc, (uint32_t)(k - 1)};
   hipLaunchKernelGGL(k_cmp_scan_reduce<NodeSrc>, dim3((unsigned)nt_nodes), dim3(CMP_NT), 0, st,
                      ns, n, sums);
   hipLaunchKernelGGL(k_cmp_scan_sums, dim3(1), dim3(1024), 0, st, sums, nt_nodes, totals);
-  const ChainSink cs{lenc, chain_of_head, o.chain_head, o.chain_len, o.chain_cyclic,
+  const ChainSink cs{lenc, head_info, o.chain_head, o.chain_len, o.chain_cyclic,
                      o.label_offsets};
   hipLaunchKernelGGL((k_cmp_scan_apply<NodeSrc, ChainSink>), dim3((unsigned)nt_nodes),
                      dim3(CMP_NT), 0, st, ns, n, sums, cs);
   hipLaunchKernelGGL(k_cmp_chain_totals, dim3(1), dim3(1), 0, st, totals, o.label_offsets,
                      o.label_capacity, res);
   hipLaunchKernelGGL(k_cmp_labels<K>, dim3(cmp_grid(n, 16384)), dim3(CMP_NT), 0, st, keys, n, k,
-                     head, chain_of_head, o.node_rank, o.node_orient, o.label_offsets,
-                     o.label_capacity, o.node_chain, o.labels, res);
+                     head, head_info, o.node_rank, o.node_orient, o.label_capacity,
+                     o.node_chain, o.labels, res);
   // kept edges in row order
   if (m) {
-    hipLaunchKernelGGL(k_cmp_edges, dim3(cmp_grid(m, 16384)), dim3(CMP_NT), 0, st, edge_node,
-                       orient, m, n, off, o.node_rank, o.node_orient, lenc, keep, res);
     const uint64_t nt_edges = m / CMP_TILE + 1;
     const EdgeSrc es{keep};
     hipLaunchKernelGGL(k_cmp_scan_reduce<EdgeSrc>, dim3((unsigned)nt_edges), dim3(CMP_NT), 0, st,
                        es, m, sums);
     hipLaunchKernelGGL(k_cmp_scan_sums, dim3(1), dim3(1024), 0, st, sums, nt_edges, totals + 2);
-    const KeptSink ks{edge_node, orient, o.node_chain, o.node_orient, n,
+    const KeptSink ks{edge_bucket, o.node_chain, o.node_orient, n,
                       o.kept_row, o.kept_u, o.kept_v, o.kept_orient};
     hipLaunchKernelGGL((k_cmp_scan_apply<EdgeSrc, KeptSink>), dim3((unsigned)nt_edges),
                        dim3(CMP_NT), 0, st, es, m, sums, ks);
@@ -723,9 +756,9 @@ size_t dbg_compact_workspace_bytes(uint64_t n_nodes, uint64_t n_edges) {
   return dbg::cmp_layout(n_nodes, n_edges).total;
 }
 
-int dbg_compact(const void *node_kmer, uint64_t n_nodes, const uint8_t *edge_orient,
-                uint64_t n_edges, int k, const uint64_t *adj_offsets, const uint32_t *inc_edge,
-                const uint8_t *inc_end, const uint32_t *edge_node, uint32_t min_nodes,
+int dbg_compact(const void *node_kmer, uint64_t n_nodes, uint64_t n_edges, int k,
+                const uint64_t *adj_offsets, const uint32_t *inc_edge, const uint8_t *inc_end,
+                const uint32_t *edge_bucket, uint32_t min_nodes,
                 const dbg_chains_t *out, dbg_compact_result_t *result, void *workspace,
                 size_t workspace_bytes, hipStream_t stream) {
   if (k < 1 || k > 63 || (k & 1) == 0) return DBG_E_K;
@@ -734,7 +767,7 @@ int dbg_compact(const void *node_kmer, uint64_t n_nodes, const uint8_t *edge_ori
                   !out->node_orient || !out->chain_head || !out->chain_len ||
                   !out->chain_cyclic || !out->labels))
     return DBG_E_NULL;
-  if (n_edges && (!edge_orient || !inc_edge || !inc_end || !edge_node || !out->kept_row ||
+  if (n_edges && (!inc_edge || !inc_end || !edge_bucket || !out->kept_row ||
                   !out->kept_u || !out->kept_v || !out->kept_orient))
     return DBG_E_NULL;
   if (n_edges && !n_nodes) return DBG_E_ARG;
@@ -745,11 +778,11 @@ int dbg_compact(const void *node_kmer, uint64_t n_nodes, const uint8_t *edge_ori
   if (3 * L.rounds + 4 > dbg::CMP_MAX_COUNTERS) return DBG_E_INTERNAL;
   char *ws = static_cast<char *>(workspace);
   const hipError_t e =
-      k <= 31 ? dbg::run_compact<uint64_t>(node_kmer, n_nodes, edge_orient, n_edges, k,
-                                           adj_offsets, inc_edge, inc_end, edge_node, min_nodes,
+      k <= 31 ? dbg::run_compact<uint64_t>(node_kmer, n_nodes, n_edges, k, adj_offsets,
+                                           inc_edge, inc_end, edge_bucket, min_nodes,
                                            *out, L, result, ws, stream)
-              : dbg::run_compact<unsigned __int128>(node_kmer, n_nodes, edge_orient, n_edges, k,
-                                                    adj_offsets, inc_edge, inc_end, edge_node,
+              : dbg::run_compact<unsigned __int128>(node_kmer, n_nodes, n_edges, k, adj_offsets,
+                                                    inc_edge, inc_end, edge_bucket,
                                                     min_nodes, *out, L, result, ws, stream);
   return e == hipSuccess ? DBG_OK : DBG_E_HIP;
 }

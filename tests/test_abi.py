@@ -134,13 +134,13 @@ def test_compact_host_checks(lib):
     vp = ctypes.c_void_p(256)
 
     def call(n=10, m=20, k=31, out=full, ws=vp, wsb=1 << 30, enode=vp, res=vp):
-        return lib.dbg_compact(vp, n, vp, m, k, vp, vp, vp, enode, 3,
+        return lib.dbg_compact(vp, n, m, k, vp, vp, vp, enode, 3,
                                ctypes.byref(out) if out is not None else None, res, ws, wsb, None)
     assert call(k=4) == 2                     # DBG_E_K
     assert call(out=None) == 1                # DBG_E_NULL
     assert call(res=None) == 1
     assert call(out=no_labels) == 1           # labels needed with nodes
-    assert call(enode=None) == 1              # edge_node needed with edges
+    assert call(enode=None) == 1              # edge_bucket needed with edges
     assert call(n=0) == 9                     # edges without nodes: DBG_E_ARG
     assert call(n=1 << 31) == 4               # DBG_E_OVERFLOW
     assert call(wsb=16) == 6                  # DBG_E_WORKSPACE

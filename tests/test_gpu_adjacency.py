@@ -29,19 +29,23 @@ def compare_adjacency(bases, offsets, k, label):
     say(f"[gpu-adjacency] {label} k={k} reads={len(offsets) - 1}")
     g, _ = gpu_graph(bases, offsets, k)
     assert g.status == 0
-    a = api.adjacency(g, edge_nodes=True)
+    a = api.adjacency(g, edge_buckets=True)
     off, ie, ien = a.to_numpy()
     ref = oracle.build_graph(bases, offsets, k)
     roff, rie, rien = graph_adjacency(ref)
     assert np.array_equal(off, roff), f"{label}: offsets differ"
     assert np.array_equal(ie, rie), f"{label}: edge rows differ"
     assert np.array_equal(ien, rien), f"{label}: ends differ"
-    # node rows of both ends of every edge
+    # buckets of both ends of every edge: 2 * node row + side (u end on side o1,
+    # v end on side 1 - o2)
     row = {(int(x), int(y)): i for i, (x, y) in enumerate(ref.node_key)}
-    want = np.array([[row[(int(a0), int(a1))], row[(int(b0), int(b1))]]
-                     for (a0, a1), (b0, b1) in zip(ref.edge_u, ref.edge_v)], np.uint32).reshape(-1)
-    got = a.edge_node.cpu().numpy().view(np.uint32)
-    assert np.array_equal(got, want), f"{label}: edge node rows differ"
+    o = ref.edge_orient.astype(np.int64)
+    want = np.array([[2 * row[(int(a0), int(a1))] + (oo >> 1),
+                      2 * row[(int(b0), int(b1))] + 1 - (oo & 1)]
+                     for (a0, a1), (b0, b1), oo in zip(ref.edge_u, ref.edge_v, o)],
+                    np.uint32).reshape(-1)
+    got = a.edge_bucket.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want), f"{label}: edge end buckets differ"
 
 
 def _rs(reads):

@@ -35,7 +35,7 @@ def gpu_compact(bases, offsets, k, min_nodes):
     from paper_1003_1940_amd import api
     g, _ = gpu_graph(bases, offsets, k)
     assert g.status == 0
-    adj = api.adjacency(g, edge_nodes=True)
+    adj = api.adjacency(g, edge_buckets=True)
     return g, api.compact(g, adj, min_nodes)
 
 
@@ -129,7 +129,7 @@ def test_compact_fullsize_properties():
     rs = synth.plain_repeats()
     g = api.build(rs.bases, rs.offsets, 31)
     assert g.status == 0
-    adj = api.adjacency(g, edge_nodes=True)
+    adj = api.adjacency(g, edge_buckets=True)
     c = api.compact(g, adj, 3)
     n, m = g.n_nodes, g.n_edges
     say(f"[gpu-compact] {n} nodes -> {c.n_chains} chains, {c.n_kept} kept edges, "
