@@ -105,34 +105,35 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_init(uint32_t *counters, uint32_
   for (uint64_t v = t0; v < n; v += (uint64_t)gridDim.x * CMP_NT) cycmin[v] = CMP_NIL;
 }
 
-// One record per state: its link (the bucket at the other end of the candidate
-// edge on the side the state leaves by, or NIL) and its jump word, in one 16-byte
-// line, so that a walk step reads the one and writes the other in the same line.
-struct alignas(16) SRec {
-  uint32_t link;
-  uint32_t spare;
-  uint64_t word;
-};
-
 template <typename K>
 __device__ __forceinline__ K state_kmer(const K *keys, uint32_t s, int k) {
   const K key = keys[s >> 1];
   return (s & 1u) ? revcomp(key, k) : key;
 }
 
+// A node's place in its chain, as a walk finds it: the chain's first node, the
+// node's rank and orientation along the canonical walk, the chain length.
+// head = NIL: not placed by a walk (a single node, or a long list or cycle that
+// pointer jumping ranks).
+struct alignas(16) NRec {
+  uint32_t head;
+  uint32_t rank;
+  uint32_t len;
+  uint32_t orient;
+};
+
 // Per node v: the links of both sides s -- the bucket at the other end of the
 // edge whose end is alone on side s of v, when that end too is alone on its side
-// and the edge is not a self-loop; NIL otherwise -- and the first jump words of
-// both states (pointer = predecessor, pred(2v + t) = link of side 1 - t; heads
-// are done at once).  A node linked on one side only ends a chain: its state
-// with a successor but no predecessor heads a list and is recorded in the
-// workgroup's own segment of `heads` (nodes [blockIdx.x * chunk, ...) give at
-// most that many heads; no global atomics).
+// and the edge is not a self-loop; NIL otherwise -- and an empty place record.
+// A node linked on one side only ends a chain: its state with a successor but no
+// predecessor heads a list and is recorded in the workgroup's own segment of
+// `heads` (nodes [blockIdx.x * chunk, ...) give at most that many heads; no
+// global atomics).
 __global__ __launch_bounds__(CMP_NT) void k_cmp_links(const uint64_t *off, uint64_t n,
                                                       const uint32_t *inc_edge,
                                                       const uint8_t *inc_end,
                                                       const uint32_t *edge_bucket, uint64_t m,
-                                                      uint64_t chunk, SRec *rec,
+                                                      uint64_t chunk, uint32_t *link, NRec *place,
                                                       uint32_t *heads, uint32_t *seg_count,
                                                       dbg_compact_result_t *res) {
   __shared__ uint32_t seg;
@@ -159,9 +160,8 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_links(const uint64_t *off, uint6
       }
       l[s] = out;
     }
-    rec[2 * v] = SRec{l[0], 0u, l[1] != CMP_NIL ? jword(l[1], 0u, 1u) : jword(CMP_NIL, 1u, 0u)};
-    rec[2 * v + 1] =
-        SRec{l[1], 0u, l[0] != CMP_NIL ? jword(l[0], 0u, 1u) : jword(CMP_NIL, 1u, 0u)};
+    reinterpret_cast<uint2 *>(link)[v] = make_uint2(l[0], l[1]);
+    place[v] = NRec{CMP_NIL, 0u, 0u, 0u};
     if ((l[0] == CMP_NIL) != (l[1] == CMP_NIL)) {
       const uint32_t h = (uint32_t)(2 * v) + (l[0] != CMP_NIL ? 0u : 1u);
       heads[v0 + atomicAdd(&seg, 1u)] = h;
@@ -171,16 +171,16 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_links(const uint64_t *off, uint6
   if (threadIdx.x == 0) seg_count[blockIdx.x] = seg;
 }
 
-// Every list head walks its list, ranking its first CMP_WALK states directly
-// (each state of a list is reached by one walk, once).  Longer lists and cycles
-// are left to pointer jumping, which continues from the ranked states.  A walk
-// that reaches the end of its list knows both heads of the chain (its own and
-// the twin's, the state after the tail's twin); it records in its head's rank
-// field whether its copy is the canonical one (1) or not (2); 0 stays for lists
-// too long to walk.  Each lane takes a new head from its workgroup's segment as
-// soon as its walk ends (one flat loop, so lanes do not wait for each other).
+// Both ends of every chain walk it, reading links only, up to CMP_WALK states.
+// A walk that reaches the tail knows the chain's length and its other end (the
+// twin copy starts at the tail's twin); of the two copies the one whose first
+// k-mer is smaller is canonical, and only that copy's walker walks again,
+// writing every node's place.  Longer lists are left to pointer jumping.  A lane
+// takes a new head from its workgroup's segment as soon as its walk ends (one
+// flat loop, so lanes do not wait for each other).
 template <typename K>
-__global__ __launch_bounds__(CMP_NT) void k_cmp_walk(SRec *rec, const uint32_t *heads,
+__global__ __launch_bounds__(CMP_NT) void k_cmp_walk(const uint32_t *link, NRec *place,
+                                                     const uint32_t *heads,
                                                      const uint32_t *seg_count, uint64_t chunk,
                                                      const K *keys, int k) {
   __shared__ uint32_t next;
@@ -188,38 +188,64 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_walk(SRec *rec, const uint32_t *
   __syncthreads();
   const uint32_t c = seg_count[blockIdx.x];
   const uint32_t *seg = heads + blockIdx.x * chunk;
-  uint32_t h = CMP_NIL, b = CMP_NIL, last = 0, r = 0;
+  uint32_t h = 0, x = 0, b = CMP_NIL, r = 0, len = 0;
+  int phase = 0;  // 0: take a head, 1: find the tail, 2: place the nodes
   while (true) {
-    if (b == CMP_NIL || r >= CMP_WALK) {
-      if (h != CMP_NIL && b == CMP_NIL) {  // the walk reached the tail `last`
-        const K a = state_kmer(keys, h, k), z = state_kmer(keys, last ^ 1u, k);
-        rec[h].word = jword(CMP_NIL, 1u, a < z ? 1u : 2u);
-      }
+    if (phase == 0) {
       const uint32_t j = atomicAdd(&next, 1u);
       if (j >= c) break;
       h = seg[j];
-      b = rec[h].link;  // bucket entered by the successor
-      last = h;
+      x = h;
+      b = link[h];  // bucket entered by the successor (never NIL for a head here)
       r = 1;
-      continue;
+      phase = 1;
+    } else if (phase == 1) {
+      if (b == CMP_NIL) {  // x is the tail; r states
+        const K a = state_kmer(keys, h, k), z = state_kmer(keys, x ^ 1u, k);
+        if (a < z) {
+          len = r;
+          x = h;
+          r = 0;
+          phase = 2;
+        } else {
+          phase = 0;
+        }
+      } else if (r >= CMP_WALK) {
+        phase = 0;
+      } else {
+        x = b ^ 1u;  // the state that enters by that bucket's side
+        b = link[x];
+        ++r;
+      }
+    } else {
+      place[x >> 1] = NRec{h >> 1, r, len, x & 1u};
+      if (++r == len) phase = 0;
+      else x = link[x] ^ 1u;
     }
-    const uint32_t x = b ^ 1u;  // the state that enters by that bucket's side
-    rec[x].word = jword(h, 1u, r);
-    last = x;
-    b = rec[x].link;
-    ++r;
   }
 }
 
-// States not ranked by a walk go on the first worklist.
-__global__ __launch_bounds__(CMP_NT) void k_cmp_pending(const SRec *rec, uint64_t n,
+// Nodes that no walk placed and that are linked: their states get first jump
+// words (pointer = predecessor, pred(2v + t) = link of side 1 - t; heads are done
+// at once) and the pending ones go on the first worklist.
+__global__ __launch_bounds__(CMP_NT) void k_cmp_pending(const uint32_t *link, const NRec *place,
+                                                        uint64_t n, uint64_t *word,
                                                         uint32_t *list, uint32_t *count) {
   __shared__ uint32_t lds[CMP_NT / 64 + 1];
   const uint64_t ns = 2 * n;
   for (uint64_t base = blockIdx.x * (uint64_t)CMP_NT; base < ns;
        base += (uint64_t)gridDim.x * CMP_NT) {
     const uint64_t x = base + threadIdx.x;
-    const bool keep = x < ns && !jdone(rec[x].word);
+    bool keep = false;
+    if (x < ns) {
+      const uint64_t v = x >> 1;
+      const uint2 l = reinterpret_cast<const uint2 *>(link)[v];
+      if (place[v].head == CMP_NIL && (l.x != CMP_NIL || l.y != CMP_NIL)) {
+        const uint32_t p = (x & 1u) ? l.x : l.y;
+        keep = p != CMP_NIL;
+        word[x] = keep ? jword(p, 0u, 1u) : jword(CMP_NIL, 1u, 0u);
+      }
+    }
     block_append(keep, (uint32_t)x, list, count, lds);
   }
 }
@@ -229,7 +255,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_pending(const SRec *rec, uint64_
 __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
                                                            const uint32_t *in_count,
                                                            uint32_t *out, uint32_t *out_count,
-                                                           SRec *rec, uint64_t ns,
+                                                           uint64_t *word, uint64_t ns,
                                                            dbg_compact_result_t *res) {
   __shared__ uint32_t lds[CMP_NT / 64 + 1];
   const uint64_t c = *in_count;
@@ -240,12 +266,12 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
     uint32_t x = 0;
     if (i < c) {
       x = in[i];
-      const uint64_t w = rec[x].word;  // only this thread writes it
+      const uint64_t w = word[x];  // only this thread writes word[x]
       const uint32_t y = jptr(w);
       if (y >= ns) {  // a pending state always points at a state
         cmp_status(res, DBG_E_INTERNAL);
       } else {
-        const uint64_t wy = load_relaxed(&rec[y].word);
+        const uint64_t wy = load_relaxed(&word[y]);
         uint64_t r = (uint64_t)jrank(w) + jrank(wy);
         if (r > 0x7fffffffull) r = 0x7fffffffull;  // only on cycles, re-ranked later
         uint64_t nw;
@@ -255,7 +281,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
           nw = jword(jptr(wy), 0u, (uint32_t)r);
           keep = true;
         }
-        store_relaxed(&rec[x].word, nw);
+        store_relaxed(&word[x], nw);
       }
     }
     block_append(keep, x, out, out_count, lds);
@@ -264,42 +290,44 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_rank_round(const uint32_t *in,
 
 // Cycle states: word = (predecessor, smallest node seen so far).
 __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_init(const uint32_t *list,
-                                                         const uint32_t *count, SRec *rec) {
+                                                         const uint32_t *count,
+                                                         const uint32_t *link, uint64_t *word) {
   const uint64_t c = *count;
   for (uint64_t i = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; i < c;
        i += (uint64_t)gridDim.x * CMP_NT) {
     const uint32_t x = list[i];
-    const uint32_t p = rec[x ^ 1u].link;  // NIL only after a bug; k_cmp_cyc_round flags it
+    const uint32_t p = link[x ^ 1u];  // NIL only after a bug; k_cmp_cyc_round flags it
     const uint32_t lo = (x >> 1) < (p >> 1) ? (x >> 1) : (p >> 1);
-    rec[x].word = ((uint64_t)p << 32) | lo;
+    word[x] = ((uint64_t)p << 32) | lo;
   }
 }
 
 __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_round(const uint32_t *list,
-                                                          const uint32_t *count, SRec *rec,
+                                                          const uint32_t *count, uint64_t *word,
                                                           uint64_t ns,
                                                           dbg_compact_result_t *res) {
   const uint64_t c = *count;
   for (uint64_t i = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; i < c;
        i += (uint64_t)gridDim.x * CMP_NT) {
     const uint32_t x = list[i];
-    const uint64_t w = rec[x].word;
+    const uint64_t w = word[x];
     const uint32_t y = (uint32_t)(w >> 32);
     if (y >= ns) {  // cycle states point at cycle states
       cmp_status(res, DBG_E_INTERNAL);
       continue;
     }
-    const uint64_t wy = load_relaxed(&rec[y].word);
+    const uint64_t wy = load_relaxed(&word[y]);
     const uint32_t a = (uint32_t)w, b = (uint32_t)wy;
-    store_relaxed(&rec[x].word, (wy & 0xffffffff00000000ull) | (a < b ? a : b));
+    store_relaxed(&word[x], (wy & 0xffffffff00000000ull) | (a < b ? a : b));
   }
 }
 
 // Break every cycle at its smallest node v: v+ heads the cycle through it, and
 // the state after v- heads the twin.  Node v's smallest cycle node is recorded.
 __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
-                                                          const uint32_t *count, SRec *rec,
-                                                          uint64_t n, uint32_t *cycmin,
+                                                          const uint32_t *count,
+                                                          const uint32_t *link, uint64_t n,
+                                                          uint64_t *word, uint32_t *cycmin,
                                                           uint32_t *out, uint32_t *out_count,
                                                           dbg_compact_result_t *res) {
   __shared__ uint32_t lds[CMP_NT / 64 + 1];
@@ -311,19 +339,19 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
     uint32_t x = 0;
     if (i < c) {
       x = list[i];
-      const uint32_t lo = (uint32_t)rec[x].word;
-      const uint32_t l1 = lo < n ? rec[2 * (uint64_t)lo + 1].link : CMP_NIL;
+      const uint32_t lo = (uint32_t)word[x];
+      const uint32_t l1 = lo < n ? link[2 * (uint64_t)lo + 1] : CMP_NIL;
       if (l1 == CMP_NIL) {  // the smallest node of a cycle is linked on both sides
         cmp_status(res, DBG_E_INTERNAL);
-        rec[x].word = jword(CMP_NIL, 1u, 0u);
+        word[x] = jword(CMP_NIL, 1u, 0u);
       } else {
         if ((x & 1u) == 0) cycmin[x >> 1] = lo;
         const uint32_t h1 = 2 * lo, h2 = l1 ^ 1u;
         if (x == h1 || x == h2) {
-          rec[x].word = jword(CMP_NIL, 1u, 0u);
+          word[x] = jword(CMP_NIL, 1u, 0u);
           if (x == h1) atomicAdd((unsigned long long *)&res->n_cyclic, 1ull);
         } else {
-          rec[x].word = jword(rec[x ^ 1u].link, 0u, 1u);
+          word[x] = jword(link[x ^ 1u], 0u, 1u);
           keep = true;
         }
       }
@@ -333,13 +361,16 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_cyc_break(const uint32_t *list,
 }
 
 // Per node: its chain's first node, its rank and orientation along the chain's
-// canonical walk, and its chain's length with bit 31 = cyclic.  The node also
-// marks the edges merged into its chain (keep = 0): the candidate edge on each
-// linked side, written by the edge's u end only, except the edge that closed a
-// broken cycle (the one leaving the chain's last node and entering its first).
+// canonical walk, and its chain's length with bit 31 = cyclic -- from its place
+// record, or for a single node directly, or from the jump words of its two
+// states.  The node also marks the edges merged into its chain (keep = 0): the
+// candidate edge on each linked side, written by the edge's u end only, except
+// the edge that closed a broken cycle (the one leaving the chain's last node and
+// entering its first).
 template <typename K>
 __global__ __launch_bounds__(CMP_NT) void k_cmp_nodes(const K *keys, uint64_t n, int k,
-                                                      uint32_t min_nodes, const SRec *rec,
+                                                      uint32_t min_nodes, const uint32_t *link,
+                                                      const NRec *place, const uint64_t *word,
                                                       const uint32_t *cycmin,
                                                       const uint64_t *off,
                                                       const uint32_t *inc_edge,
@@ -352,45 +383,48 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_nodes(const K *keys, uint64_t n,
     cmp_status(res, DBG_E_INTERNAL);
   for (uint64_t v = blockIdx.x * (uint64_t)CMP_NT + threadIdx.x; v < n;
        v += (uint64_t)gridDim.x * CMP_NT) {
-    const SRec s0 = rec[2 * v], s1 = rec[2 * v + 1];
-    const uint64_t w0 = s0.word, w1 = s1.word;
-    uint32_t h0 = jptr(w0) == CMP_NIL ? (uint32_t)(2 * v) : jptr(w0);
-    uint32_t h1 = jptr(w1) == CMP_NIL ? (uint32_t)(2 * v + 1) : jptr(w1);
-    if (h0 >= 2 * n || h1 >= 2 * n) {  // only after a failed ranking
-      cmp_status(res, DBG_E_INTERNAL);
-      h0 = (uint32_t)(2 * v);
-      h1 = (uint32_t)(2 * v + 1);
-    }
-    // a head's rank field holds its walk's verdict, not a rank
-    const uint32_t r0 = jptr(w0) == CMP_NIL ? 0u : jrank(w0);
-    const uint32_t r1 = jptr(w1) == CMP_NIL ? 0u : jrank(w1);
-    uint32_t len = r0 + r1 + 1, rank = 0, o = 0, hd = (uint32_t)v, cyc = 0;
-    if (len > 1) {
+    const uint2 l = reinterpret_cast<const uint2 *>(link)[v];
+    const NRec p = place[v];
+    uint32_t len = 1, rank = 0, o = 0, hd = (uint32_t)v, cyc = 0;
+    if (p.head != CMP_NIL) {
+      hd = p.head;
+      rank = p.rank;
+      len = p.len;
+      o = p.orient;
+    } else if (l.x != CMP_NIL || l.y != CMP_NIL) {
+      const uint64_t w0 = word[2 * v], w1 = word[2 * v + 1];
+      uint32_t h0 = jptr(w0) == CMP_NIL ? (uint32_t)(2 * v) : jptr(w0);
+      uint32_t h1 = jptr(w1) == CMP_NIL ? (uint32_t)(2 * v + 1) : jptr(w1);
+      if (h0 >= 2 * n || h1 >= 2 * n) {  // only after a failed ranking
+        cmp_status(res, DBG_E_INTERNAL);
+        h0 = (uint32_t)(2 * v);
+        h1 = (uint32_t)(2 * v + 1);
+      }
+      const uint32_t r0 = jrank(w0), r1 = jrank(w1);
+      len = r0 + r1 + 1;
       const uint32_t lo = cycmin[v];
       bool first;
       if (lo != CMP_NIL) {
         first = h0 == 2 * lo;
         cyc = 1;
       } else {
-        const uint32_t verdict = jrank(rec[h0].word) & 3u;
-        first = verdict == 1u ||
-                (verdict == 0u && state_kmer(keys, h0, k) < state_kmer(keys, h1, k));
+        first = state_kmer(keys, h0, k) < state_kmer(keys, h1, k);
       }
       o = first ? 0u : 1u;
       rank = first ? r0 : r1;
       hd = (first ? h0 : h1) >> 1;
-      if (len < min_nodes) {
-        len = 1;
-        rank = o = cyc = 0;
-        hd = (uint32_t)v;
-      }
+    }
+    if (len > 1 && len < min_nodes) {
+      len = 1;
+      rank = o = cyc = 0;
+      hd = (uint32_t)v;
     }
     node_rank[v] = rank;
     node_orient[v] = (uint8_t)o;
     head[v] = hd;
     lenc[v] = len | (cyc << 31);
     if (len > 1) {
-      const uint32_t links[2] = {s0.link, s1.link};
+      const uint32_t links[2] = {l.x, l.y};
       for (uint32_t s = 0; s < 2; ++s) {
         if (links[s] == CMP_NIL) continue;
         const uint64_t at = off[2 * v + s];
@@ -619,7 +653,7 @@ static inline unsigned cmp_grid(uint64_t n, uint64_t cap) {
 static inline size_t cmp_align(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct CmpLayout {
-  size_t rec, list0, list1, counters, cycmin, head, lenc, head_info, keep, sums, totals,
+  size_t link, word, place, list0, list1, counters, cycmin, head, lenc, head_info, keep, sums, totals,
       heads, seg_count, total;
   int rounds;
   uint64_t tiles, chunk, segments;
@@ -644,7 +678,9 @@ static CmpLayout cmp_layout(uint64_t n, uint64_t m) {
     off = cmp_align(off + (bytes ? bytes : 1));
     return o;
   };
-  L.rec = take(2 * n * sizeof(SRec));
+  L.link = take(2 * n * sizeof(uint32_t));
+  L.word = take(2 * n * sizeof(uint64_t));
+  L.place = take(n * sizeof(NRec));
   L.list0 = take(2 * n * sizeof(uint32_t));
   L.list1 = take(2 * n * sizeof(uint32_t));
   L.counters = take(CMP_MAX_COUNTERS * sizeof(uint32_t));
@@ -668,7 +704,9 @@ static hipError_t run_compact(const void *node_kmer, uint64_t n, uint64_t m, int
                               uint32_t min_nodes, const dbg_chains_t &o, const CmpLayout &L,
                               dbg_compact_result_t *res, char *ws, hipStream_t st) {
   const K *keys = static_cast<const K *>(node_kmer);
-  SRec *rec = reinterpret_cast<SRec *>(ws + L.rec);
+  uint32_t *link = reinterpret_cast<uint32_t *>(ws + L.link);
+  uint64_t *word = reinterpret_cast<uint64_t *>(ws + L.word);
+  NRec *place = reinterpret_cast<NRec *>(ws + L.place);
   uint32_t *list[2] = {reinterpret_cast<uint32_t *>(ws + L.list0),
                        reinterpret_cast<uint32_t *>(ws + L.list1)};
   uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + L.counters);
@@ -690,32 +728,34 @@ static hipError_t run_compact(const void *node_kmer, uint64_t n, uint64_t m, int
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_cmp_links, dim3((unsigned)L.segments), dim3(CMP_NT), 0, st, off, n,
-                     inc_edge, inc_end, edge_bucket, m, L.chunk, rec, heads, seg_count, res);
-  hipLaunchKernelGGL(k_cmp_walk<K>, dim3((unsigned)L.segments), dim3(CMP_NT), 0, st, rec, heads,
-                     seg_count, L.chunk, keys, k);
-  hipLaunchKernelGGL(k_cmp_pending, dim3(cmp_grid(2 * n, 8192)), dim3(CMP_NT), 0, st, rec, n,
-                     list[0], &cnt[0]);
+                     inc_edge, inc_end, edge_bucket, m, L.chunk, link, place, heads, seg_count,
+                     res);
+  hipLaunchKernelGGL(k_cmp_walk<K>, dim3((unsigned)L.segments), dim3(CMP_NT), 0, st, link, place,
+                     heads, seg_count, L.chunk, keys, k);
+  hipLaunchKernelGGL(k_cmp_pending, dim3(cmp_grid(2 * n, 8192)), dim3(CMP_NT), 0, st, link, place,
+                     n, word, list[0], &cnt[0]);
   // lists: rounds 0 .. R-1 move states from list[r & 1] (count cnt[r]) to
   // list[(r + 1) & 1] (count cnt[r + 1])
   for (int r = 0; r < R; ++r)
     hipLaunchKernelGGL(k_cmp_rank_round, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, list[r & 1],
-                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], rec, 2 * n, res);
+                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], word, 2 * n, res);
   // cycles: the states left in list[R & 1]
   uint32_t *cl = list[R & 1];
-  hipLaunchKernelGGL(k_cmp_cyc_init, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R], rec);
+  hipLaunchKernelGGL(k_cmp_cyc_init, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R], link,
+                     word);
   for (int r = 0; r < R; ++r)
     hipLaunchKernelGGL(k_cmp_cyc_round, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R],
-                       rec, 2 * n, res);
+                       word, 2 * n, res);
   hipLaunchKernelGGL(k_cmp_cyc_break, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, cl, &cnt[R],
-                     rec, n, cycmin, list[(R + 1) & 1], &cnt[R + 1], res);
+                     link, n, word, cycmin, list[(R + 1) & 1], &cnt[R + 1], res);
   for (int r = R + 1; r <= 2 * R; ++r)
     hipLaunchKernelGGL(k_cmp_rank_round, dim3(CMP_ROUND_GRID), dim3(CMP_NT), 0, st, list[r & 1],
-                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], rec, 2 * n, res);
+                       &cnt[r], list[(r + 1) & 1], &cnt[r + 1], word, 2 * n, res);
   if (m)
     hipLaunchKernelGGL(k_cmp_fill_u8, dim3(cmp_grid(m, 8192)), dim3(CMP_NT), 0, st, keep, m,
                        (uint8_t)1);
   hipLaunchKernelGGL(k_cmp_nodes<K>, dim3(cmp_grid(n, 16384)), dim3(CMP_NT), 0, st, keys, n, k,
-                     min_nodes, rec, cycmin, off, inc_edge, inc_end, m, o.node_rank,
+                     min_nodes, link, place, word, cycmin, off, inc_edge, inc_end, m, o.node_rank,
                      o.node_orient, head, lenc, keep, &cnt[2 * R + 1], res);
   // chains in the order of their first node; label offsets
   const uint64_t nt_nodes = n / CMP_TILE + 1;
