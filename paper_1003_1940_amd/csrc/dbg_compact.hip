@@ -122,6 +122,20 @@ struct alignas(16) NRec {
   uint32_t orient;
 };
 
+// Bit b of `single` is set when bucket b holds exactly one end: one bucket per
+// lane, a wave's 64 bits assembled by a ballot (read as 32-bit words, little
+// endian).
+__global__ __launch_bounds__(CMP_NT) void k_cmp_single(const uint64_t *off, uint64_t nb,
+                                                       uint64_t *single) {
+  for (uint64_t base = blockIdx.x * (uint64_t)CMP_NT; base < nb;
+       base += (uint64_t)gridDim.x * CMP_NT) {
+    const uint64_t b = base + threadIdx.x;
+    const bool one = b < nb && off[b + 1] == off[b] + 1;
+    const uint64_t bits = __ballot(one);
+    if (lane_id() == 0) single[b >> 6] = bits;
+  }
+}
+
 // Per node v: the links of both sides s -- the bucket at the other end of the
 // edge whose end is alone on side s of v, when that end too is alone on its side
 // and the edge is not a self-loop; NIL otherwise -- and an empty place record.
@@ -133,7 +147,8 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_links(const uint64_t *off, uint6
                                                       const uint32_t *inc_edge,
                                                       const uint8_t *inc_end,
                                                       const uint32_t *edge_bucket, uint64_t m,
-                                                      uint64_t chunk, uint32_t *link, NRec *place,
+                                                      const uint32_t *single, uint64_t chunk,
+                                                      uint32_t *link, NRec *place,
                                                       uint32_t *heads, uint32_t *seg_count,
                                                       dbg_compact_result_t *res) {
   __shared__ uint32_t seg;
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(CMP_NT) void k_cmp_links(const uint64_t *off, uint6
         } else {
           const uint32_t bw = edge_bucket[2 * (uint64_t)e + (t ^ 1u)];  // the other end
           if (bw >= 2 * n) cmp_status(res, DBG_E_ARG);
-          else if ((uint64_t)(bw >> 1) != v && off[bw + 1] == off[bw] + 1) out = bw;
+          else if ((uint64_t)(bw >> 1) != v && ((single[bw >> 5] >> (bw & 31u)) & 1u)) out = bw;
         }
       }
       l[s] = out;
@@ -639,6 +654,35 @@ struct KeptSink {
   }
 };
 
+// Kept edges in row order: every thread takes 16 consecutive keep flags (0 or
+// 1) as one vector, the workgroup scans their counts, and only the kept edges
+// are visited.
+__global__ __launch_bounds__(CMP_NT) void k_cmp_kept_apply(const uint8_t *keep, uint64_t m,
+                                                           const uint64_t *sums, KeptSink sink) {
+  __shared__ uint64_t wsum[CMP_NT / 64 + 1];
+  const uint64_t base = blockIdx.x * CMP_TILE + threadIdx.x * (uint64_t)16;
+  uint32_t mask = 0;
+  if (base + 16 <= m) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(keep + base);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) mask |= ((w[i] >> (8 * j)) & 1u) << (4 * i + j);
+  } else {
+    for (int r = 0; r < 16; ++r)
+      if (base + r < m && keep[base + r]) mask |= 1u << r;
+  }
+  uint64_t tot;
+  uint64_t pos = block_exclusive_scan<CMP_NT>((uint64_t)__popc(mask), wsum, &tot) +
+                 sums[2 * blockIdx.x];
+  while (mask) {
+    const int r = __ffs(mask) - 1;
+    mask &= mask - 1;
+    sink(base + r, pos++, 0, 1);
+  }
+}
+
 __global__ void k_cmp_kept_total(const uint64_t *totals, dbg_compact_result_t *res) {
   if (threadIdx.x || blockIdx.x) return;
   res->n_kept = totals[0];
@@ -653,7 +697,7 @@ static inline unsigned cmp_grid(uint64_t n, uint64_t cap) {
 static inline size_t cmp_align(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct CmpLayout {
-  size_t link, word, place, list0, list1, counters, cycmin, head, lenc, head_info, keep, sums, totals,
+  size_t link, word, place, single, list0, list1, counters, cycmin, head, lenc, head_info, keep, sums, totals,
       heads, seg_count, total;
   int rounds;
   uint64_t tiles, chunk, segments;
@@ -681,6 +725,7 @@ static CmpLayout cmp_layout(uint64_t n, uint64_t m) {
   L.link = take(2 * n * sizeof(uint32_t));
   L.word = take(2 * n * sizeof(uint64_t));
   L.place = take(n * sizeof(NRec));
+  L.single = take((2 * n + 63) / 64 * sizeof(uint64_t) + CMP_NT / 8);
   L.list0 = take(2 * n * sizeof(uint32_t));
   L.list1 = take(2 * n * sizeof(uint32_t));
   L.counters = take(CMP_MAX_COUNTERS * sizeof(uint32_t));
@@ -707,6 +752,7 @@ static hipError_t run_compact(const void *node_kmer, uint64_t n, uint64_t m, int
   uint32_t *link = reinterpret_cast<uint32_t *>(ws + L.link);
   uint64_t *word = reinterpret_cast<uint64_t *>(ws + L.word);
   NRec *place = reinterpret_cast<NRec *>(ws + L.place);
+  uint32_t *single = reinterpret_cast<uint32_t *>(ws + L.single);
   uint32_t *list[2] = {reinterpret_cast<uint32_t *>(ws + L.list0),
                        reinterpret_cast<uint32_t *>(ws + L.list1)};
   uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + L.counters);
@@ -727,9 +773,11 @@ static hipError_t run_compact(const void *node_kmer, uint64_t n, uint64_t m, int
     hipLaunchKernelGGL(k_cmp_empty, dim3(1), dim3(1), 0, st, o.label_offsets);
     return hipGetLastError();
   }
+  hipLaunchKernelGGL(k_cmp_single, dim3(cmp_grid(2 * n, 16384)), dim3(CMP_NT), 0, st, off,
+                     2 * n, reinterpret_cast<uint64_t *>(single));
   hipLaunchKernelGGL(k_cmp_links, dim3((unsigned)L.segments), dim3(CMP_NT), 0, st, off, n,
-                     inc_edge, inc_end, edge_bucket, m, L.chunk, link, place, heads, seg_count,
-                     res);
+                     inc_edge, inc_end, edge_bucket, m, single, L.chunk, link, place, heads,
+                     seg_count, res);
   hipLaunchKernelGGL(k_cmp_walk<K>, dim3((unsigned)L.segments), dim3(CMP_NT), 0, st, link, place,
                      heads, seg_count, L.chunk, keys, k);
   hipLaunchKernelGGL(k_cmp_pending, dim3(cmp_grid(2 * n, 8192)), dim3(CMP_NT), 0, st, link, place,
@@ -781,8 +829,8 @@ static hipError_t run_compact(const void *node_kmer, uint64_t n, uint64_t m, int
     hipLaunchKernelGGL(k_cmp_scan_sums, dim3(1), dim3(1024), 0, st, sums, nt_edges, totals + 2);
     const KeptSink ks{edge_bucket, o.node_chain, o.node_orient, n,
                       o.kept_row, o.kept_u, o.kept_v, o.kept_orient};
-    hipLaunchKernelGGL((k_cmp_scan_apply<EdgeSrc, KeptSink>), dim3((unsigned)nt_edges),
-                       dim3(CMP_NT), 0, st, es, m, sums, ks);
+    hipLaunchKernelGGL(k_cmp_kept_apply, dim3((unsigned)nt_edges), dim3(CMP_NT), 0, st, keep, m,
+                       sums, ks);
     hipLaunchKernelGGL(k_cmp_kept_total, dim3(1), dim3(1), 0, st, totals + 2, res);
   }
   return hipGetLastError();
