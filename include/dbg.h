@@ -214,6 +214,45 @@ int dbg_set_tuning(const dbg_tuning_t *tuning);
 /* Copies the current tuning into *tuning (DBG_E_NULL if null). */
 int dbg_get_tuning(dbg_tuning_t *tuning);
 
+/* Key-space slices (the out-of-memory build, Sec. 6).  The paper sorts more
+ * keys than fit in memory as sorted runs merged R ways.  Here a build keeps only
+ * the keys whose top DBG_PREFIX_BITS bits (the prefix of the canonical
+ * (k+1)-mer for the edge table, of the canonical k-mer for the node table) lie
+ * in [prefix_lo, prefix_hi).  Slices of disjoint, increasing prefix ranges give
+ * disjoint, increasing parts of both sorted tables, so the tables of a sequence
+ * of slices covering [0, DBG_PREFIX_BINS) concatenate to the full tables: no
+ * merge.  Each slice re-reads the packed reads (2 bits per base) and needs key
+ * buffers only for its own keys.
+ *
+ * dbg_prefix_counts: edge_counts / node_counts (device, DBG_PREFIX_BINS uint64_t
+ * each) receive the number of (k+1)-mer / k-mer positions of each prefix, from
+ * which a caller plans slices that fit a key budget.  max_positions bounds the
+ * k-mer positions (n_bases always does); result->status reports DBG_E_OFFSETS
+ * or DBG_E_OVERFLOW.  Workspace: dbg_prefix_workspace_bytes.
+ *
+ * dbg_build_slice: dbg_build restricted to the prefixes [prefix_lo, prefix_hi);
+ * max_positions bounds the positions (as max_keys does for dbg_build), max_keys
+ * the keys each table keeps (result->status = DBG_E_OVERFLOW when a table has
+ * more; the slice must then be split).  The node table always enumerates
+ * k-mers (the edge-endpoint route needs the whole edge table).  Host errors as
+ * dbg_build, and DBG_E_ARG for max_keys > max_positions or a bad range.
+ * Workspace: dbg_slice_workspace_bytes.  Both enqueue on `stream` and never
+ * synchronise or allocate. */
+#define DBG_PREFIX_BITS 12
+#define DBG_PREFIX_BINS (1u << DBG_PREFIX_BITS)
+size_t dbg_prefix_workspace_bytes(uint64_t n_reads, uint64_t max_positions, int k);
+int dbg_prefix_counts(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                      uint64_t n_reads, int k, uint64_t max_positions, uint64_t *edge_counts,
+                      uint64_t *node_counts, dbg_result_t *result, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+size_t dbg_slice_workspace_bytes(uint64_t n_reads, uint64_t max_positions, uint64_t max_keys,
+                                 int k);
+int dbg_build_slice(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                    uint64_t n_reads, int k, uint64_t max_positions, uint64_t max_keys,
+                    uint32_t prefix_lo, uint32_t prefix_hi, const dbg_nodes_t *nodes,
+                    const dbg_edges_t *edges, dbg_result_t *result, void *workspace,
+                    size_t workspace_bytes, hipStream_t stream);
+
 /* STEP-4 of Sec. 3: adjacency lists of a built graph.  A node has two sides:
  * side 0, by which a walk reading its canonical k-mer forward leaves it, and
  * side 1, by which such a walk enters it.  A distinct edge (u, v, o1, o2) leaves

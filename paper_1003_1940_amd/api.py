@@ -92,6 +92,16 @@ def load():
         lib.dbg_adjacency.restype = i32
         lib.dbg_adjacency.argtypes = [vp, u64, vp, vp, vp, u64, i32, vp, vp, vp, vp, vp, vp, sz,
                                       vp]
+        lib.dbg_prefix_workspace_bytes.restype = sz
+        lib.dbg_prefix_workspace_bytes.argtypes = [u64, u64, i32]
+        lib.dbg_prefix_counts.restype = i32
+        lib.dbg_prefix_counts.argtypes = [vp, u64, vp, u64, i32, u64, vp, vp, vp, vp, sz, vp]
+        lib.dbg_slice_workspace_bytes.restype = sz
+        lib.dbg_slice_workspace_bytes.argtypes = [u64, u64, u64, i32]
+        lib.dbg_build_slice.restype = i32
+        lib.dbg_build_slice.argtypes = [vp, u64, vp, u64, i32, u64, u64, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.POINTER(_Nodes),
+                                        ctypes.POINTER(_Edges), vp, vp, sz, vp]
         lib.dbg_compact_workspace_bytes.restype = sz
         lib.dbg_compact_workspace_bytes.argtypes = [u64, u64]
         lib.dbg_compact.restype = i32

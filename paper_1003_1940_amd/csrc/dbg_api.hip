@@ -17,7 +17,8 @@ static dbg_tuning_t current_tuning() {
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) {
+Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
+                   uint64_t max_positions) {
   Layout L{};
   L.key_bytes = k <= 31 ? 8 : 16;
   // list capacities follow from the smallest batch any workgroup shape takes
@@ -25,7 +26,7 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) 
       k <= 31 ? local_cap<uint64_t, true, 1>() : local_cap<unsigned __int128, true, 1>();
   const int edge_bits = 2 * (k + 1);
   const uint64_t levels = (uint64_t)((edge_bits + 7) / 8);  // digit levels incl. level 0
-  L.max_tiles = (max_keys + TILE - 1) / TILE + n_sets;
+  L.max_tiles = (max_positions + TILE - 1) / TILE + n_sets;
   L.item_cap = max_keys / cap + 2;
   // batches per level <= 2 * keys / cap + parents + oversized children
   L.batch_cap = levels * (2 * (max_keys / cap) + 1) + n_sets + 3 * levels * L.item_cap + 64;
@@ -84,7 +85,7 @@ static int check_common(uint64_t n_bases, const uint64_t *packed, const uint64_t
 }
 
 static int run(const BuildArgs &a, size_t workspace_bytes) {
-  const Layout L = make_layout(a.n_reads, a.n_sets, a.max_keys, a.k);
+  const Layout L = make_layout(a.n_reads, a.n_sets, a.max_keys, a.k, a.max_positions);
   if (workspace_bytes < L.total) return DBG_E_WORKSPACE;
   const hipError_t e = a.k <= 31 ? run_build_u64(a, L) : run_build_u128(a, L);
   return e == hipSuccess ? DBG_OK : DBG_E_HIP;
@@ -96,7 +97,13 @@ extern "C" {
 
 size_t dbg_workspace_bytes(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k) {
   if (k < 1 || k > 63 || (k & 1) == 0 || n_sets == 0) return 0;
-  return dbg::make_layout(n_reads, n_sets, max_keys, k).total;
+  return dbg::make_layout(n_reads, n_sets, max_keys, k, max_keys).total;
+}
+
+size_t dbg_slice_workspace_bytes(uint64_t n_reads, uint64_t max_positions, uint64_t max_keys,
+                                 int k) {
+  if (k < 1 || k > 63 || (k & 1) == 0 || max_keys > max_positions) return 0;
+  return dbg::make_layout(n_reads, 1, max_keys, k, max_positions).total;
 }
 
 int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
@@ -114,6 +121,9 @@ int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_off
   a.set_read_offsets = nullptr;
   a.n_sets = 1;
   a.max_keys = max_keys;
+  a.max_positions = max_keys;
+  a.pfx_lo = 0;
+  a.pfx_hi = dbg::PFX_BINS;
   a.k = k;
   a.nodes = *nodes;
   a.edges = *edges;
@@ -143,6 +153,9 @@ int dbg_build_batched(const uint64_t *packed, uint64_t n_bases, const uint64_t *
   a.set_read_offsets = set_read_offsets;
   a.n_sets = n_sets;
   a.max_keys = max_keys;
+  a.max_positions = max_keys;
+  a.pfx_lo = 0;
+  a.pfx_hi = dbg::PFX_BINS;
   a.k = k;
   a.nodes = *nodes;
   a.edges = *edges;
@@ -153,6 +166,72 @@ int dbg_build_batched(const uint64_t *packed, uint64_t n_bases, const uint64_t *
   a.stream = stream;
   a.tuning = dbg::current_tuning();
   return dbg::run(a, workspace_bytes);
+}
+
+int dbg_build_slice(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                    uint64_t n_reads, int k, uint64_t max_positions, uint64_t max_keys,
+                    uint32_t prefix_lo, uint32_t prefix_hi, const dbg_nodes_t *nodes,
+                    const dbg_edges_t *edges, dbg_result_t *result, void *workspace,
+                    size_t workspace_bytes, hipStream_t stream) {
+  const int c = dbg::check_common(n_bases, packed, read_offsets, k, max_keys, nodes, edges, result,
+                                  workspace);
+  if (c != DBG_OK) return c;
+  if (max_positions >= (1ull << 32)) return DBG_E_OVERFLOW;
+  if (max_keys > max_positions || prefix_lo > prefix_hi || prefix_hi > DBG_PREFIX_BINS)
+    return DBG_E_ARG;
+  dbg::BuildArgs a{};
+  a.packed = packed;
+  a.n_bases = n_bases;
+  a.read_offsets = read_offsets;
+  a.n_reads = n_reads;
+  a.set_read_offsets = nullptr;
+  a.n_sets = 1;
+  a.max_keys = max_keys;
+  a.max_positions = max_positions;
+  a.pfx_lo = prefix_lo;
+  a.pfx_hi = prefix_hi;
+  a.k = k;
+  a.nodes = *nodes;
+  a.edges = *edges;
+  a.result = result;
+  a.workspace = workspace;
+  a.stream = stream;
+  a.tuning = dbg::current_tuning();
+  return dbg::run(a, workspace_bytes);
+}
+
+size_t dbg_prefix_workspace_bytes(uint64_t n_reads, uint64_t max_positions, int k) {
+  if (k < 1 || k > 63 || (k & 1) == 0) return 0;
+  return dbg::make_layout(n_reads, 1, 0, k, max_positions).total;
+}
+
+int dbg_prefix_counts(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                      uint64_t n_reads, int k, uint64_t max_positions, uint64_t *edge_counts,
+                      uint64_t *node_counts, dbg_result_t *result, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream) {
+  if (!read_offsets || !edge_counts || !node_counts || !result || !workspace) return DBG_E_NULL;
+  if (n_bases && !packed) return DBG_E_NULL;
+  if (k < 1 || k > 63 || (k & 1) == 0) return DBG_E_K;
+  if (max_positions >= (1ull << 32)) return DBG_E_OVERFLOW;
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return DBG_E_WORKSPACE;
+  const dbg::Layout L = dbg::make_layout(n_reads, 1, 0, k, max_positions);
+  if (workspace_bytes < L.total) return DBG_E_WORKSPACE;
+  dbg::BuildArgs a{};
+  a.packed = packed;
+  a.n_bases = n_bases;
+  a.read_offsets = read_offsets;
+  a.n_reads = n_reads;
+  a.n_sets = 1;
+  a.max_keys = 0;
+  a.max_positions = max_positions;
+  a.pfx_lo = 0;
+  a.pfx_hi = dbg::PFX_BINS;
+  a.k = k;
+  a.result = result;
+  a.workspace = workspace;
+  a.stream = stream;
+  return dbg::run_prefix_counts(a, L, edge_counts, node_counts) == hipSuccess ? DBG_OK
+                                                                              : DBG_E_HIP;
 }
 
 int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,

@@ -37,6 +37,12 @@ template <typename K, bool W = false, int V = 0> constexpr uint64_t local_cap() 
 }
 constexpr int LOCAL_VARIANTS = 2;
 
+// Key-space slices: a build can keep only the keys whose top PFX_BITS bits (the
+// prefix) lie in [pfx_lo, pfx_hi); slices of disjoint prefix ranges give disjoint
+// parts of both sorted tables.
+constexpr int PFX_BITS = 12;
+constexpr uint32_t PFX_BINS = 1u << PFX_BITS;
+
 // Most-significant-digit levels: level 0 is the enumeration scatter; a key of b
 // bits has ceil(b / 8) digits.
 constexpr int MAX_LEVELS = 16;
@@ -78,7 +84,10 @@ struct Layout {
   int key_bytes;
 };
 
-Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k);
+// max_positions bounds the k-mer positions the enumeration visits, max_keys the
+// keys a table keeps (the same unless the build is a key-space slice).
+Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
+                   uint64_t max_positions);
 
 struct BuildArgs {
   const uint64_t *packed;
@@ -88,6 +97,8 @@ struct BuildArgs {
   const uint64_t *set_read_offsets;  // null: one set
   uint64_t n_sets;
   uint64_t max_keys;
+  uint64_t max_positions;  // >= max_keys; > max_keys only for a slice
+  uint32_t pfx_lo, pfx_hi;  // key prefixes kept: [pfx_lo, pfx_hi) of [0, PFX_BINS)
   int k;
   dbg_nodes_t nodes;
   dbg_edges_t edges;
@@ -101,6 +112,9 @@ struct BuildArgs {
 
 hipError_t run_build_u64(const BuildArgs &a, const Layout &L);
 hipError_t run_build_u128(const BuildArgs &a, const Layout &L);
+// Counts of the canonical (k+1)-mer and k-mer prefixes (PFX_BINS each, uint64).
+hipError_t run_prefix_counts(const BuildArgs &a, const Layout &L, uint64_t *edge_counts,
+                             uint64_t *node_counts);
 void set_stage_events(hipEvent_t *events);
 hipError_t launch_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
                        dbg_result_t *result, hipStream_t stream);

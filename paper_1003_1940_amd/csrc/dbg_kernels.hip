@@ -173,14 +173,14 @@ __global__ __launch_bounds__(SCAN_NT) void k_read_apply(const uint64_t *off, uin
 // Per-set key ranges and enumeration tiles.  One workgroup.
 __global__ __launch_bounds__(1024) void k_set_setup(const uint64_t *rbase, uint64_t n_reads,
                                                     const uint64_t *set_read_off, uint64_t n_sets,
-                                                    uint64_t max_keys, uint64_t *set_kbase,
+                                                    uint64_t max_positions, uint64_t *set_kbase,
                                                     uint64_t *set_tbase, Ctl *ctl) {
   __shared__ uint64_t wsum[1024 / 64 + 1];
   if (ctl->status) return;
   if (threadIdx.x == 0) {
     const uint64_t nk = rbase[n_reads];
     ctl->n_keys = nk;
-    if (nk > max_keys) set_status(ctl, DBG_E_OVERFLOW);
+    if (nk > max_positions) set_status(ctl, DBG_E_OVERFLOW);
     if (set_read_off[0] != 0 || set_read_off[n_sets] != n_reads) set_status(ctl, DBG_E_OFFSETS);
   }
   uint64_t carry = 0;
@@ -239,7 +239,19 @@ struct EnumArgs {
   int len;   // bases per key
   int bits;  // 2 * len
   int gate;
+  uint32_t pfx_lo, pfx_hi;  // keys kept: prefix in [pfx_lo, pfx_hi)
 };
+
+// The top PFX_BITS bits of a key of `bits` bits (zero-extended when shorter).
+template <typename K> __device__ __forceinline__ uint32_t key_prefix_bits(K key, int bits) {
+  return bits >= PFX_BITS ? (uint32_t)shr<K>(key, bits - PFX_BITS)
+                          : (uint32_t)key << (PFX_BITS - bits);
+}
+
+template <typename K> __device__ __forceinline__ bool in_slice(const EnumArgs &a, K key) {
+  const uint32_t p = key_prefix_bits(key, a.bits);
+  return p >= a.pfx_lo && p < a.pfx_hi;
+}
 
 struct TileRange {
   uint64_t start, end, read_lo, read_hi;
@@ -380,7 +392,9 @@ __device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, u
   return n;
 }
 
-template <typename K>
+// SL: the build is a key-space slice (keys outside [pfx_lo, pfx_hi) are dropped);
+// full builds compile the test out.
+template <typename K, bool SL>
 __global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint32_t *thist,
                                                          const Ctl *ctl) {
   __shared__ uint32_t h[256];
@@ -395,9 +409,50 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint32_t *t
                                          tr.end, tr.read_lo, tr.read_hi, keys);
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r)
-    if (r < n) atomicAdd(&h[msd_digit(keys[r], a.bits, 0)], 1u);
+    if (r < n && (!SL || in_slice(a, keys[r]))) atomicAdd(&h[msd_digit(keys[r], a.bits, 0)], 1u);
   __syncthreads();
   thist[t * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// Keys kept by the table (the totals row of the column prefix): the table's key
+// count, bounded by the key buffers.
+__global__ void k_kept_keys(const uint32_t *thist, uint64_t max_keys, Ctl *ctl, int gate) {
+  __shared__ uint64_t wsum[256 / 64 + 1];
+  if (ctl->status || gated_off(ctl, gate)) return;
+  const uint64_t nt = ctl->n_tiles;
+  uint64_t tot;
+  block_exclusive_scan<256>((uint64_t)thist[nt * 256 + threadIdx.x], wsum, &tot);
+  if (threadIdx.x == 0) {
+    ctl->n_keys = tot;
+    if (tot > max_keys) set_status(ctl, DBG_E_OVERFLOW);
+  }
+}
+
+// Prefix counts over whole read sets: each workgroup takes tiles t = blockIdx.x,
+// blockIdx.x + gridDim.x, ..., counts their keys' prefixes in LDS and adds the
+// counts to the global ones once.
+template <typename K>
+__global__ __launch_bounds__(STREAM_NT) void k_prefix_hist(EnumArgs a, uint64_t *counts,
+                                                           const Ctl *ctl) {
+  __shared__ uint32_t h[PFX_BINS];
+  __shared__ EnumLds L;
+  if (ctl->status) return;
+  for (uint32_t i = threadIdx.x; i < PFX_BINS; i += STREAM_NT) h[i] = 0;
+  const uint64_t nt = ctl->n_tiles;
+  for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    __syncthreads();  // the previous tile's staged words are dead
+    const TileRange tr = enum_tile(a, t);
+    const TileSrc ts = stage_tile(a, tr, L);
+    K keys[STREAM_KPT];
+    const int n = enum_keys<K, STREAM_KPT>(a, ts, tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
+                                           tr.end, tr.read_lo, tr.read_hi, keys);
+#pragma unroll
+    for (int r = 0; r < STREAM_KPT; ++r)
+      if (r < n) atomicAdd(&h[key_prefix_bits(keys[r], a.bits)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < PFX_BINS; i += STREAM_NT)
+    if (h[i]) atomicAdd((unsigned long long *)&counts[i], (unsigned long long)h[i]);
 }
 
 // Column-wise exclusive prefix of the per-tile histograms over all tiles:
@@ -505,7 +560,8 @@ template <typename K, bool W = false>
 __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
                                                const uint32_t (&wts)[STREAM_KPT], int n, int bits,
                                                int level, uint64_t *cursor, uint64_t my_base,
-                                               K *dst, uint32_t *dstw, PartLds<K, W> &s) {
+                                               K *dst, uint32_t *dstw, PartLds<K, W> &s,
+                                               uint32_t valid = 0xffffffffu) {
   // cursor != null: reserve each digit's range with one atomic on cursor[d];
   // otherwise thread d already holds its digit's destination start in my_base.
   const uint32_t tid = threadIdx.x;
@@ -516,7 +572,7 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r)
-    if (r < n) atomicAdd(&s.cnt[dig[r]], 1u);
+    if (r < n && ((valid >> r) & 1u)) atomicAdd(&s.cnt[dig[r]], 1u);
   __syncthreads();
   const uint64_t c = s.cnt[tid];
   uint64_t m;
@@ -531,7 +587,7 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r)
-    if (r < n) {
+    if (r < n && ((valid >> r) & 1u)) {
       const uint32_t q = atomicAdd(&s.cnt[dig[r]], 1u);
       s.keys[q] = keys[r];
       if (W) s.wts[q] = wts[r];
@@ -548,7 +604,7 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
 
 // Second enumeration pass: keys go to cursor0[set][d] plus the number of keys
 // with digit d in the set's earlier tiles (from the tile prefix), so no atomics.
-template <typename K>
+template <typename K, bool SL>
 __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const uint64_t *cursor0,
                                                             const uint32_t *tpre, K *dst,
                                                             const Ctl *ctl) {
@@ -569,7 +625,14 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
   const uint64_t base = cursor0[(uint64_t)tr.set * 256 + d] +
                         (uint32_t)(tpre[t * 256 + d] - tpre[t_first * 256 + d]);
   const uint32_t nowt[STREAM_KPT] = {};
-  partition_tile<K>(keys, nowt, n, a.bits, 0, nullptr, base, dst, nullptr, s);
+  uint32_t valid = 0xffffffffu;
+  if (SL) {
+    valid = 0;
+#pragma unroll
+    for (int r = 0; r < STREAM_KPT; ++r)
+      if (r < n && in_slice(a, keys[r])) valid |= 1u << r;
+  }
+  partition_tile<K>(keys, nowt, n, a.bits, 0, nullptr, base, dst, nullptr, s, valid);
 }
 
 // ---------------------------------------------------------------------------
@@ -1940,7 +2003,8 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   // The node table of a single-set build may be built from the edge endpoints
   // instead of the k-mers; the device picks the route (k_node_path) and the
   // kernels of the other route return at once.  g0 gates the k-mer route.
-  const bool two_routes = !edges && S == 1 && A.tuning.node_path != DBG_NODES_KMERS;
+  const bool sliced = A.pfx_lo != 0 || A.pfx_hi != PFX_BINS;
+  const bool two_routes = !edges && S == 1 && A.tuning.node_path != DBG_NODES_KMERS && !sliced;
   const int g0 = two_routes ? 0 : -1;
   const uint64_t n_words = (A.n_bases + 31) / 32;
   // workgroup shape of the LDS bucket sort, and the batch capacity it plans for
@@ -1957,7 +2021,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   hipLaunchKernelGGL(k_read_apply, dim3((unsigned)L.read_blocks), dim3(SCAN_NT), 0, st,
                      A.read_offsets, A.n_reads, len, block_sums, rbase, ctl);
   hipLaunchKernelGGL(k_set_setup, dim3(1), dim3(1024), 0, st, rbase, A.n_reads, set_read_off, S,
-                     A.max_keys, set_kbase, set_tbase, ctl);
+                     A.max_positions, set_kbase, set_tbase, ctl);
   hipLaunchKernelGGL(k_tile_map, dim3(grid_for(L.max_tiles, 256, 1u << 30)), dim3(256), 0, st,
                      rbase, set_read_off, S, set_kbase, set_tbase, tile_read, tile_set,
                      L.max_tiles, ctl);
@@ -1968,9 +2032,13 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                        L.key_bytes);
   stage(ev + 1, st);
   EnumArgs ea{A.packed, n_words, A.read_offsets, rbase, set_read_off, set_kbase,
-              set_tbase, tile_read, tile_set, len, bits, g0};
-  hipLaunchKernelGGL(k_enum_hist<K>, dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st, ea,
-                     thist, ctl);
+              set_tbase, tile_read, tile_set, len, bits, g0, A.pfx_lo, A.pfx_hi};
+  if (sliced)
+    hipLaunchKernelGGL((k_enum_hist<K, true>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st,
+                       ea, thist, ctl);
+  else
+    hipLaunchKernelGGL((k_enum_hist<K, false>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0,
+                       st, ea, thist, ctl);
   if (two_routes) {
     const K *eu = static_cast<const K *>(A.edges.u);
     hipLaunchKernelGGL(k_rec_edges<K>, dim3(grid_for(A.edges.capacity, 256, 8192)), dim3(256), 0,
@@ -1985,6 +2053,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, &ctl->n_tiles, ctl, g0);
   hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum,
                      &ctl->n_tiles, ctl, g0);
+  hipLaunchKernelGGL(k_kept_keys, dim3(1), dim3(256), 0, st, thist, A.max_keys, ctl, g0);
   // column prefix of the per-tile digit counts of a level in tile mode
   const unsigned lcol_chunks =
       (unsigned)((L.max_tiles + L.item_cap + COL_CHUNK - 1) / COL_CHUNK);
@@ -2016,8 +2085,12 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                        pw, la0);
   }
   stage(ev + 3, st);
-  hipLaunchKernelGGL(k_enum_scatter<K>, dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st, ea,
-                     cursor0, thist, x0, ctl);
+  if (sliced)
+    hipLaunchKernelGGL((k_enum_scatter<K, true>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0,
+                       st, ea, cursor0, thist, x0, ctl);
+  else
+    hipLaunchKernelGGL((k_enum_scatter<K, false>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0,
+                       st, ea, cursor0, thist, x0, ctl);
   if (two_routes)
     hipLaunchKernelGGL((k_level_scatter<K, true>), dim3(level_grid), dim3(STREAM_NT), 0, st, la0,
                        x0, x1, ctl);
@@ -2118,6 +2191,55 @@ static hipError_t run_build(const BuildArgs &A, const Layout &L) {
                      A.set_read_offsets ? 0 : 1);
   hipError_t e = run_table<K>(A, L, true);
   if (e == hipSuccess) e = run_table<K>(A, L, false);
+  hipLaunchKernelGGL(k_write_result, dim3(1), dim3(1), 0, A.stream, ctl, A.result);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e;
+}
+
+// Key offsets and tiles of one key length, then the prefix counts of its keys.
+template <typename K>
+static hipError_t run_prefix(const BuildArgs &A, const Layout &L, int len, uint64_t *counts) {
+  char *ws = static_cast<char *>(A.workspace);
+  Ctl *ctl = reinterpret_cast<Ctl *>(ws + L.ctl);
+  uint64_t *set_read_off = reinterpret_cast<uint64_t *>(ws + L.set_read_off);
+  uint64_t *rbase = reinterpret_cast<uint64_t *>(ws + L.rbase);
+  uint64_t *block_sums = reinterpret_cast<uint64_t *>(ws + L.block_sums);
+  uint64_t *set_kbase = reinterpret_cast<uint64_t *>(ws + L.set_kbase);
+  uint64_t *set_tbase = reinterpret_cast<uint64_t *>(ws + L.set_tbase);
+  uint64_t *tile_read = reinterpret_cast<uint64_t *>(ws + L.tile_read);
+  uint32_t *tile_set = reinterpret_cast<uint32_t *>(ws + L.tile_set);
+  hipStream_t st = A.stream;
+  hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(1), 0, st, ctl);
+  hipLaunchKernelGGL(k_read_reduce, dim3((unsigned)L.read_blocks), dim3(SCAN_NT), 0, st,
+                     A.read_offsets, A.n_reads, A.n_bases, len, block_sums, ctl);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, block_sums, L.read_blocks,
+                     (uint64_t *)nullptr);
+  hipLaunchKernelGGL(k_read_apply, dim3((unsigned)L.read_blocks), dim3(SCAN_NT), 0, st,
+                     A.read_offsets, A.n_reads, len, block_sums, rbase, ctl);
+  hipLaunchKernelGGL(k_set_setup, dim3(1), dim3(1024), 0, st, rbase, A.n_reads, set_read_off,
+                     (uint64_t)1, A.max_positions, set_kbase, set_tbase, ctl);
+  hipLaunchKernelGGL(k_tile_map, dim3(grid_for(L.max_tiles, 256, 1u << 30)), dim3(256), 0, st,
+                     rbase, set_read_off, (uint64_t)1, set_kbase, set_tbase, tile_read, tile_set,
+                     L.max_tiles, ctl);
+  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, st, counts, (uint64_t)PFX_BINS, 0ull);
+  EnumArgs ea{A.packed, (A.n_bases + 31) / 32, A.read_offsets, rbase, set_read_off, set_kbase,
+              set_tbase, tile_read, tile_set, len, 2 * len, -1, 0u, PFX_BINS};
+  hipLaunchKernelGGL(k_prefix_hist<K>, dim3(grid_for(L.max_tiles, 1, 2048)), dim3(STREAM_NT), 0,
+                     st, ea, counts, ctl);
+  return hipGetLastError();
+}
+
+hipError_t run_prefix_counts(const BuildArgs &A, const Layout &L, uint64_t *edge_counts,
+                             uint64_t *node_counts) {
+  char *ws = static_cast<char *>(A.workspace);
+  Ctl *ctl = reinterpret_cast<Ctl *>(ws + L.ctl);
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(1), 0, A.stream, ctl,
+                     reinterpret_cast<uint64_t *>(ws + L.set_read_off), A.n_reads, 1);
+  hipError_t e = A.k <= 31 ? run_prefix<uint64_t>(A, L, A.k + 1, edge_counts)
+                           : run_prefix<u128>(A, L, A.k + 1, edge_counts);
+  if (e == hipSuccess)
+    e = A.k <= 31 ? run_prefix<uint64_t>(A, L, A.k, node_counts)
+                  : run_prefix<u128>(A, L, A.k, node_counts);
   hipLaunchKernelGGL(k_write_result, dim3(1), dim3(1), 0, A.stream, ctl, A.result);
   if (e == hipSuccess) e = hipGetLastError();
   return e;

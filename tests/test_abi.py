@@ -25,9 +25,11 @@ def lib():
 
 def test_header_declares_entry_points():
     assert declared_functions() == ["dbg_adjacency", "dbg_adjacency_workspace_bytes",
-                                    "dbg_build", "dbg_build_batched", "dbg_compact",
-                                    "dbg_compact_workspace_bytes", "dbg_get_tuning",
-                                    "dbg_pack_ascii", "dbg_set_stage_events", "dbg_set_tuning",
+                                    "dbg_build", "dbg_build_batched", "dbg_build_slice",
+                                    "dbg_compact", "dbg_compact_workspace_bytes",
+                                    "dbg_get_tuning", "dbg_pack_ascii", "dbg_prefix_counts",
+                                    "dbg_prefix_workspace_bytes", "dbg_set_stage_events",
+                                    "dbg_set_tuning", "dbg_slice_workspace_bytes",
                                     "dbg_strerror", "dbg_workspace_bytes"]
 
 
@@ -145,3 +147,36 @@ def test_compact_host_checks(lib):
     assert call(n=1 << 31) == 4               # DBG_E_OVERFLOW
     assert call(wsb=16) == 6                  # DBG_E_WORKSPACE
     assert call(ws=ctypes.c_void_p(257)) == 6
+
+
+def test_slice_host_checks(lib):
+    """dbg_build_slice / dbg_prefix_counts argument checks on the host."""
+    from paper_1003_1940_amd import api
+    v = ctypes.c_void_p(256)
+    assert lib.dbg_slice_workspace_bytes(10, 1000, 100, 31) > 0
+    assert lib.dbg_slice_workspace_bytes(10, 1000, 2000, 31) == 0   # max_keys > positions
+    assert lib.dbg_slice_workspace_bytes(10, 1000, 100, 8) == 0     # even k
+    # the slice workspace grows with its keys, not with the positions alone
+    assert lib.dbg_slice_workspace_bytes(10, 10**8, 10**6, 31) < \
+        lib.dbg_workspace_bytes(10, 1, 10**8, 31) / 4
+    assert lib.dbg_prefix_workspace_bytes(10, 1000, 31) > 0
+    nodes = api._Nodes(256, 256, 10)
+    edges = api._Edges(256, 256, 256, 256, None, 10)
+
+    def call(k=31, mp=1000, mk=100, lo=0, hi=4096, ws=v, wsb=1 << 30):
+        return lib.dbg_build_slice(v, 100, v, 10, k, mp, mk, lo, hi, ctypes.byref(nodes),
+                                   ctypes.byref(edges), v, ws, wsb, None)
+    assert call(k=4) == 2                    # DBG_E_K
+    assert call(mk=2000) == 9                # max_keys > max_positions: DBG_E_ARG
+    assert call(lo=10, hi=5) == 9            # empty range reversed
+    assert call(hi=4097) == 9                # past the last prefix
+    assert call(mp=1 << 32) == 4             # DBG_E_OVERFLOW
+    assert call(wsb=16) == 6                 # DBG_E_WORKSPACE
+    assert call(ws=ctypes.c_void_p(257)) == 6
+
+    def pc(k=31, mp=1000, ec=v, wsb=1 << 30):
+        return lib.dbg_prefix_counts(v, 100, v, 10, k, mp, ec, v, v, v, wsb, None)
+    assert pc(k=2) == 2
+    assert pc(ec=None) == 1
+    assert pc(mp=1 << 32) == 4
+    assert pc(wsb=16) == 6
