@@ -92,6 +92,23 @@ def measured_traffic(workload, kernel):
     return row["fetch_kib"] * 1024 * data["fetch_scale"] + row["write_kib"] * 1024 * data["write_scale"]
 
 
+def measured_build_traffic(workload):
+    """HBM bytes of one whole build (every build kernel, both tables) from the
+    counter summary, scaled like measured_traffic; None when absent or stale."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    a = text.find("```json")
+    if a < 0:
+        return None
+    b = text.find("```", a + 7)
+    data = json.loads(text[a + 7:b])
+    if data.get("kernel_source_sha256") != kernel_source_hash() or "build_total" not in data:
+        return None
+    return data["build_total"]["bytes"]
+
+
 def run_copy_calibration(nbytes=1 << 30, reps=3):
     """A plain device-to-device copy of known size, for scaling the HBM counters."""
     import torch
@@ -122,7 +139,19 @@ def run_cpu_baseline(rs, k, target_s=15.0):
     kmers = sub.kmer_count(k)
     return {"value": kmers / dt, "unit": "k-mers/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sub.n_reads} reads of the workload ({kmers} k-mer positions), "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall", "cpu": cpu_model()}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), for the baseline record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_batched(args):
@@ -518,6 +547,13 @@ def main():
     lsd_gbs = lsd / (ms / 1e3) / 1e9
     build_lsd = {"bytes": round(lsd), "achieved": round(lsd_gbs, 1), "unit": "GB/s",
                  "frac": round(lsd_gbs / HBM_PEAK_GBS, 4)}
+    # the whole build's HBM bytes as the counters measured them (FETCH_SIZE +
+    # WRITE_SIZE of every build kernel), over this run's build time
+    tb = (measured_build_traffic(args.workload)
+          if zkey and args.scale == 1.0 and args.node_route == "auto" else None)
+    build_traffic = None if tb is None else {
+        "bytes": tb, "achieved": round(tb / (ms / 1e3) / 1e9, 1), "unit": "GB/s",
+        "frac": round(tb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     # STEP-4 adjacency lists and the Sec. 7 chain compaction of the built graph
     # (not part of the timed build)
@@ -570,6 +606,7 @@ def main():
     line = {
         "metric": "k-mers/s into bi-directed graph",
         "value": n_k / (ms / 1e3),
+        "keys_per_s": (n_k + n_e) / (ms / 1e3),
         "unit": "k-mers/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms,
@@ -585,6 +622,7 @@ def main():
         "stages_ms": {k_: round(v, 4) for k_, v in stages.items()},
         "sort_reduce_ms": round(sr_ms, 4),
         "build_as_lsd_d8": build_lsd,
+        "build_traffic": build_traffic,
         "adjacency": adjacency,
         "compaction": compaction,
         "tuning": tuning if tuning is not None else api.get_tuning(),
