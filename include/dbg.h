@@ -120,6 +120,16 @@ typedef struct {
  * Returns 0 for invalid k. */
 size_t dbg_workspace_bytes(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k);
 
+/* Exact worst case of a build's table sizes, on the host: the k-mer positions
+ * (sum over reads of max(0, L - k + 1), Sec. 4's n) and the (k+1)-mer positions
+ * (sum of max(0, L - k)) of reads given by host offsets[n_reads + 1].  Every
+ * node is one position's canonical k-mer and every edge one position's record,
+ * so capacities of these sizes always hold the tables; max_nodes is also the
+ * max_keys bound of dbg_workspace_bytes / dbg_build.  Errors: DBG_E_NULL,
+ * DBG_E_K, DBG_E_OFFSETS (offsets[0] != 0 or decreasing). */
+int dbg_bounds(const uint64_t *read_offsets, uint64_t n_reads, int k, uint64_t *max_nodes,
+               uint64_t *max_edges);
+
 /* Build the graph of one read set (Sec. 3, BiConstruct STEP-1 to STEP-3).
  *   packed        device, ceil(n_bases / 32) words (layout above)
  *   n_bases       bases in the stream (= read_offsets[n_reads])

@@ -92,6 +92,8 @@ def load():
         lib.dbg_adjacency.restype = i32
         lib.dbg_adjacency.argtypes = [vp, u64, vp, vp, vp, u64, i32, vp, vp, vp, vp, vp, vp, sz,
                                       vp]
+        lib.dbg_bounds.restype = i32
+        lib.dbg_bounds.argtypes = [vp, u64, i32, vp, vp]
         lib.dbg_prefix_workspace_bytes.restype = sz
         lib.dbg_prefix_workspace_bytes.argtypes = [u64, u64, i32]
         lib.dbg_prefix_counts.restype = i32
@@ -293,6 +295,19 @@ def build_async(packed, n_bases: int, offsets, k: int, max_keys: int, out: dict,
         where = "dbg_build_batched"
     if rc:
         raise DbgError(rc, where)
+
+
+def bounds(offsets: np.ndarray, k: int) -> tuple:
+    """(max_nodes, max_edges): the exact worst-case table sizes of reads given by
+    host offsets (dbg_bounds)."""
+    off = np.ascontiguousarray(offsets, np.uint64)
+    if len(off) == 0:
+        raise ValueError("offsets need at least one entry")
+    mn, me = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    rc = load().dbg_bounds(off.ctypes.data, len(off) - 1, k, ctypes.byref(mn), ctypes.byref(me))
+    if rc:
+        raise DbgError(rc, "dbg_bounds")
+    return int(mn.value), int(me.value)
 
 
 def read_result(result) -> tuple:

@@ -234,6 +234,23 @@ int dbg_prefix_counts(const uint64_t *packed, uint64_t n_bases, const uint64_t *
                                                                               : DBG_E_HIP;
 }
 
+int dbg_bounds(const uint64_t *read_offsets, uint64_t n_reads, int k, uint64_t *max_nodes,
+               uint64_t *max_edges) {
+  if (!read_offsets || !max_nodes || !max_edges) return DBG_E_NULL;
+  if (k < 1 || k > 63 || (k & 1) == 0) return DBG_E_K;
+  if (read_offsets[0] != 0) return DBG_E_OFFSETS;
+  uint64_t nk = 0, ne = 0;
+  for (uint64_t i = 0; i < n_reads; ++i) {
+    if (read_offsets[i + 1] < read_offsets[i]) return DBG_E_OFFSETS;
+    const uint64_t len = read_offsets[i + 1] - read_offsets[i];
+    if (len >= (uint64_t)k) nk += len - (uint64_t)k + 1;
+    if (len > (uint64_t)k) ne += len - (uint64_t)k;
+  }
+  *max_nodes = nk;
+  *max_edges = ne;
+  return DBG_OK;
+}
+
 int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
                    dbg_result_t *result, hipStream_t stream) {
   if (n_bases && (!ascii || !packed)) return DBG_E_NULL;

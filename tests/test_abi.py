@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -25,7 +26,8 @@ def lib():
 
 def test_header_declares_entry_points():
     assert declared_functions() == ["dbg_adjacency", "dbg_adjacency_workspace_bytes",
-                                    "dbg_build", "dbg_build_batched", "dbg_build_slice",
+                                    "dbg_bounds", "dbg_build", "dbg_build_batched",
+                                    "dbg_build_slice",
                                     "dbg_compact", "dbg_compact_workspace_bytes",
                                     "dbg_get_tuning", "dbg_pack_ascii", "dbg_prefix_counts",
                                     "dbg_prefix_workspace_bytes", "dbg_set_stage_events",
@@ -180,3 +182,20 @@ def test_slice_host_checks(lib):
     assert pc(ec=None) == 1
     assert pc(mp=1 << 32) == 4
     assert pc(wsb=16) == 6
+
+
+def test_bounds_on_the_host():
+    """dbg_bounds: exact position counts from host offsets (no device work)."""
+    from paper_1003_1940_amd import api
+    off = np.array([0, 5, 5, 8, 40, 41], np.uint64)   # lengths 5, 0, 3, 32, 1
+    for k in (1, 3, 5, 31):
+        lens = np.diff(off.astype(np.int64))
+        want = (int(np.maximum(lens - k + 1, 0).sum()), int(np.maximum(lens - k, 0).sum()))
+        assert api.bounds(off, k) == want
+    assert api.bounds(np.array([0], np.uint64), 3) == (0, 0)
+    with pytest.raises(api.DbgError):
+        api.bounds(off, 4)
+    with pytest.raises(api.DbgError):
+        api.bounds(np.array([1, 5], np.uint64), 3)
+    with pytest.raises(api.DbgError):
+        api.bounds(np.array([0, 5, 4], np.uint64), 3)
