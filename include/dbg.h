@@ -285,7 +285,9 @@ int dbg_build_slice(const uint64_t *packed, uint64_t n_bases, const uint64_t *re
  * edge_u / edge_v / edge_orient (n_edges rows), key width as in dbg_build; the
  * counts are the build's n_nodes / n_edges (read from its result record).
  * result (device) receives status DBG_OK, or DBG_E_ARG when an edge endpoint is
- * not in the node table (then the entries are not written).  Host errors:
+ * not in the node table or a (node, side) holds more than 256 ends (a side of a
+ * read set's k-mer holds at most 8: four one-base extensions, two ends each);
+ * then the entries are not written.  Host errors:
  * DBG_E_K, DBG_E_NULL, DBG_E_ARG (edges without nodes), DBG_E_OVERFLOW
  * (n_nodes >= 2^31 or n_edges >= 2^32), DBG_E_WORKSPACE.  Enqueues on `stream`,
  * never synchronises or allocates. */

@@ -17,9 +17,12 @@
 //      B-bit key prefix), so an endpoint is found by one index read and a
 //      binary search over a few rows;
 //   2. k_adj_count: each edge finds the rows of its endpoints, records the two
-//      buckets and counts them;
+//      buckets and counts them, keeping each end's arrival rank in its bucket
+//      (a side of a k-mer is an end of at most four distinct (k+1)-mers, so at
+//      most eight ends: a byte);
 //   3. k_adj_scan_*: exclusive scan of the bucket counts into the offsets;
-//   4. k_adj_scatter: each incidence takes a place in its bucket;
+//   4. k_adj_scatter: each incidence goes to its bucket's offset plus its rank
+//      (no atomics);
 //   5. k_adj_order: each bucket (at most a few entries: a side of a k-mer has
 //      at most four one-base extensions, counted for both ends of an edge) is
 //      sorted by (edge row, end).
@@ -78,7 +81,8 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_count(const K *keys, uint64_t n,
                                                       const K *eu, const K *ev,
                                                       const uint8_t *orient, uint64_t m,
                                                       uint32_t *bucket, uint32_t *counts,
-                                                      uint32_t *edge_bucket, dbg_result_t *res) {
+                                                      uint8_t *rank, uint32_t *edge_bucket,
+                                                      dbg_result_t *res) {
   for (uint64_t j = blockIdx.x * (uint64_t)ADJ_NT + threadIdx.x; j < m;
        j += (uint64_t)gridDim.x * ADJ_NT) {
     const uint32_t o = orient[j];
@@ -96,8 +100,10 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_count(const K *keys, uint64_t n,
       edge_bucket[2 * j] = bu;
       edge_bucket[2 * j + 1] = bv;
     }
-    atomicAdd(&counts[bu], 1u);
-    atomicAdd(&counts[bv], 1u);
+    const uint32_t ru = atomicAdd(&counts[bu], 1u), rv = atomicAdd(&counts[bv], 1u);
+    if (ru > 255u || rv > 255u) adj_status(res, DBG_E_ARG);  // not a read set's graph
+    rank[2 * j] = (uint8_t)ru;
+    rank[2 * j + 1] = (uint8_t)rv;
   }
 }
 
@@ -146,19 +152,17 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_scan_apply(const uint32_t *count
   }
 }
 
-// Places are taken from the top of each bucket down (the counts are consumed);
-// k_adj_order fixes the order inside the bucket.
-__global__ __launch_bounds__(ADJ_NT) void k_adj_scatter(const uint32_t *bucket, uint64_t m,
+// Each incidence goes to its bucket's offset plus its arrival rank; k_adj_order
+// fixes the order inside the bucket.
+__global__ __launch_bounds__(ADJ_NT) void k_adj_scatter(const uint32_t *bucket,
+                                                        const uint8_t *rank, uint64_t m,
                                                         const uint64_t *offsets,
-                                                        uint32_t *counts, uint32_t *inc_edge,
-                                                        uint8_t *inc_end,
+                                                        uint32_t *inc_edge, uint8_t *inc_end,
                                                         const dbg_result_t *res) {
   if (res->status) return;
   for (uint64_t t = blockIdx.x * (uint64_t)ADJ_NT + threadIdx.x; t < 2 * m;
        t += (uint64_t)gridDim.x * ADJ_NT) {
-    const uint32_t b = bucket[t];
-    const uint32_t r = atomicSub(&counts[b], 1u) - 1u;
-    const uint64_t pos = offsets[b] + r;
+    const uint64_t pos = offsets[bucket[t]] + rank[t];
     inc_edge[pos] = (uint32_t)(t >> 1);
     inc_end[pos] = (uint8_t)(t & 1);
   }
@@ -215,7 +219,7 @@ static inline unsigned adj_grid(uint64_t n, uint64_t cap) {
 static inline size_t adj_align(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct AdjLayout {
-  size_t first, bucket, counts, sums, total;
+  size_t first, bucket, counts, rank, sums, total;
   int bits, shift;
   uint32_t nbins;
 };
@@ -238,6 +242,7 @@ static AdjLayout adj_layout(uint64_t n, uint64_t m, int k) {
   L.first = take(((size_t)L.nbins + 1) * sizeof(uint32_t));
   L.bucket = take((size_t)(2 * m) * sizeof(uint32_t));
   L.counts = take((size_t)nb * sizeof(uint32_t));
+  L.rank = take((size_t)(2 * m));
   L.sums = take((size_t)(nb / ADJ_SCAN_TILE + 1) * sizeof(uint64_t));
   L.total = off;
   return L;
@@ -253,6 +258,7 @@ static hipError_t run_adjacency(const void *node_kmer, uint64_t n, const void *e
   uint32_t *first = reinterpret_cast<uint32_t *>(ws + L.first);
   uint32_t *bucket = reinterpret_cast<uint32_t *>(ws + L.bucket);
   uint32_t *counts = reinterpret_cast<uint32_t *>(ws + L.counts);
+  uint8_t *rank = reinterpret_cast<uint8_t *>(ws + L.rank);
   uint64_t *sums = reinterpret_cast<uint64_t *>(ws + L.sums);
   const uint64_t nb = 2 * n;
   const uint64_t nsum = nb / ADJ_SCAN_TILE + 1;
@@ -262,14 +268,14 @@ static hipError_t run_adjacency(const void *node_kmer, uint64_t n, const void *e
                      L.shift, L.nbins, first);
   hipLaunchKernelGGL(k_adj_count<K>, dim3(adj_grid(m, 16384)), dim3(ADJ_NT), 0, st, keys, n,
                      first, L.nbins, L.shift, static_cast<const K *>(eu), static_cast<const K *>(ev),
-                     orient, m, bucket, counts, edge_bucket, res);
+                     orient, m, bucket, counts, rank, edge_bucket, res);
   hipLaunchKernelGGL(k_adj_scan_reduce, dim3((unsigned)nsum), dim3(ADJ_NT), 0, st, counts, nb,
                      sums);
   hipLaunchKernelGGL(k_adj_scan_sums, dim3(1), dim3(1024), 0, st, sums, nsum);
   hipLaunchKernelGGL(k_adj_scan_apply, dim3((unsigned)nsum), dim3(ADJ_NT), 0, st, counts, nb,
                      sums, offsets);
-  hipLaunchKernelGGL(k_adj_scatter, dim3(adj_grid(2 * m, 16384)), dim3(ADJ_NT), 0, st, bucket, m,
-                     offsets, counts, inc_edge, inc_end, res);
+  hipLaunchKernelGGL(k_adj_scatter, dim3(adj_grid(2 * m, 16384)), dim3(ADJ_NT), 0, st, bucket,
+                     rank, m, offsets, inc_edge, inc_end, res);
   hipLaunchKernelGGL(k_adj_order, dim3(adj_grid(nb, 16384)), dim3(ADJ_NT), 0, st, offsets, nb,
                      inc_edge, inc_end, res);
   hipLaunchKernelGGL(k_adj_result, dim3(1), dim3(1), 0, st, res, n, m);
