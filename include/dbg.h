@@ -208,7 +208,9 @@ typedef struct {
   float endpoint_ratio; /* for DBG_NODES_AUTO; default 0.6 */
   /* Shape of the LDS bucket sort: 0 = 512-thread workgroups holding up to 6,144
    * keys (64-bit; 3,072 for 128-bit keys), one per CU; 1 = 256-thread
-   * workgroups holding half as many, two per CU.  Default 0. */
+   * workgroups holding half as many, two per CU; 2 = for 64-bit keys
+   * 768-thread workgroups holding 6,144 keys (three waves per SIMD instead of
+   * two), for 128-bit keys the same as 0.  Default 2. */
   int local_variant;
   /* Added to the width of the first partition of each batch's distinct keys
    * (normally log2 of their number, 8 to 11 bits), in [-3, 3].  Default 0. */

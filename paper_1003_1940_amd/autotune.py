@@ -2,8 +2,9 @@
 
 Every knob of ``dbg_tuning_t`` leaves the tables unchanged and moves only the
 time: the node-table route (k-mers or edge endpoints), the workgroup shape of the
-LDS bucket sort (512 threads with the largest batch, or 256 threads with half the
-batch and two workgroups per CU) and the bias of the first partition's digit
+LDS bucket sort (512 threads with the largest batch; 256 threads with half the
+batch and two workgroups per CU; or, for 64-bit keys, 768 threads with the
+largest batch) and the bias of the first partition's digit
 width inside a batch.  ``tune`` builds one input under every candidate setting,
 checks that all of them produce bit-identical tables, times each, and returns
 the fastest.  ``TuneCache`` keeps the choices in a JSON file keyed by an input
@@ -23,14 +24,14 @@ import numpy as np
 
 from . import api
 
-DEFAULT = {"node_path": api.NODES_AUTO, "endpoint_ratio": 0.6, "local_variant": 0,
+DEFAULT = {"node_path": api.NODES_AUTO, "endpoint_ratio": 0.6, "local_variant": 2,
            "lds_digit_bias": 0}
 
 
-def candidates(node_paths=(api.NODES_KMERS, api.NODES_ENDPOINTS), local_variants=(0, 1),
+def candidates(node_paths=(api.NODES_KMERS, api.NODES_ENDPOINTS), local_variants=(0, 1, 2),
                biases=(-1, 0, 1)) -> list:
     """The settings ``tune`` tries by default: every combination of the given
-    values (12 by default)."""
+    values (18 by default)."""
     return [dict(DEFAULT, node_path=n, local_variant=v, lds_digit_bias=b)
             for n, v, b in itertools.product(node_paths, local_variants, biases)]
 

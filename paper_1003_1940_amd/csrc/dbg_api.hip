@@ -8,7 +8,7 @@ namespace dbg {
 
 // Process-wide tuning: copied under the lock at the start of each build call.
 static std::mutex g_tuning_mu;
-static dbg_tuning_t g_tuning = {DBG_NODES_AUTO, 0.6f, 0, 0, {0, 0, 0, 0}};
+static dbg_tuning_t g_tuning = {DBG_NODES_AUTO, 0.6f, 2, 0, {0, 0, 0, 0}};
 
 static dbg_tuning_t current_tuning() {
   std::lock_guard<std::mutex> lock(g_tuning_mu);
@@ -266,7 +266,7 @@ int dbg_set_stage_events(hipEvent_t *events, int n_events) {
 }
 
 int dbg_set_tuning(const dbg_tuning_t *tuning) {
-  dbg_tuning_t t = {DBG_NODES_AUTO, 0.6f, 0, 0, {0, 0, 0, 0}};
+  dbg_tuning_t t = {DBG_NODES_AUTO, 0.6f, 2, 0, {0, 0, 0, 0}};
   if (tuning) {
     if (tuning->node_path < DBG_NODES_AUTO || tuning->node_path > DBG_NODES_ENDPOINTS)
       return DBG_E_ARG;

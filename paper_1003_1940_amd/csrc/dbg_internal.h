@@ -26,16 +26,17 @@ constexpr uint64_t TILE = (uint64_t)STREAM_NT * STREAM_KPT;
 // CU), 1 = 256 threads and half the batch (two workgroups per CU: more batches
 // in flight for small inputs, more keys left for deeper partition levels).
 template <typename K, bool W = false, int V = 0> struct LocalCfg {
-  static_assert(V == 0 || V == 1, "two workgroup shapes");
-  static constexpr int NT = V == 0 ? 512 : 256;
-  static constexpr int CAP = (sizeof(K) == 8 ? (W ? 5120 : 6144) : 3072) >> V;
+  static_assert(V >= 0 && V <= 2, "three workgroup shapes");
+  static constexpr int NT = V == 1 ? 256 : (V == 2 && sizeof(K) == 8) ? 768 : 512;
+  static constexpr int CAP = (sizeof(K) == 8 ? (W ? 5120 : 6144) : 3072) >> (V == 1 ? 1 : 0);
   static constexpr int SLOTS = CAP * 3 / 2;
   static constexpr int SMALL = sizeof(K) == 8 ? 16 : 8;  // segments sorted by one lane's network
+  static constexpr int WAVES_PER_EU = (NT / 64 + 3) / 4;
 };
 template <typename K, bool W = false, int V = 0> constexpr uint64_t local_cap() {
   return (uint64_t)LocalCfg<K, W, V>::CAP;
 }
-constexpr int LOCAL_VARIANTS = 2;
+constexpr int LOCAL_VARIANTS = 3;
 
 // Key-space slices: a build can keep only the keys whose top PFX_BITS bits (the
 // prefix) lie in [pfx_lo, pfx_hi); slices of disjoint prefix ranges give disjoint

@@ -1518,7 +1518,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
 }
 
 template <bool W, int V>
-__global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) void k_local_sort64(
+__global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdgpu_waves_per_eu(LocalCfg<uint64_t, W, V>::WAVES_PER_EU))) void k_local_sort64(
     const Batch *batches, const uint64_t *n_batches_p, uint64_t *b0, uint64_t *b1,
     const uint32_t *w0, const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate,
     int dw_bias) {
@@ -2009,8 +2009,8 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   const uint64_t n_words = (A.n_bases + 31) / 32;
   // workgroup shape of the LDS bucket sort, and the batch capacity it plans for
   const int lv = A.tuning.local_variant;
-  const uint64_t cap_u = lv == 0 ? local_cap<K, false, 0>() : local_cap<K, false, 1>();
-  const uint64_t cap_w = lv == 0 ? local_cap<K, true, 0>() : local_cap<K, true, 1>();
+  const uint64_t cap_u = lv == 1 ? local_cap<K, false, 1>() : local_cap<K, false, 0>();
+  const uint64_t cap_w = lv == 1 ? local_cap<K, true, 1>() : local_cap<K, true, 0>();
 
   stage(ev + 0, st);
   hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(1), 0, st, ctl);
@@ -2134,11 +2134,17 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     if (two_routes)
       launch_local_sort<K, true, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
                                     runbits, ctl, 1, bias);
-  } else {
+  } else if (lv == 1) {
     launch_local_sort<K, false, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, runbits,
                                    ctl, g0, bias);
     if (two_routes)
       launch_local_sort<K, true, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
+                                    runbits, ctl, 1, bias);
+  } else {
+    launch_local_sort<K, false, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, runbits,
+                                   ctl, g0, bias);
+    if (two_routes)
+      launch_local_sort<K, true, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
                                     runbits, ctl, 1, bias);
   }
   stage(ev + 6, st);

@@ -88,7 +88,7 @@ def test_tuning_round_trip(lib):
     from paper_1003_1940_amd import api
     d = api.set_tuning(defaults=True)
     assert d == {"node_path": api.NODES_AUTO, "endpoint_ratio": pytest.approx(0.6),
-                 "local_variant": 0, "lds_digit_bias": 0}
+                 "local_variant": 2, "lds_digit_bias": 0}
     assert api.set_tuning(local_variant=1, lds_digit_bias=-2)["local_variant"] == 1
     assert api.get_tuning()["lds_digit_bias"] == -2
     api.set_tuning(defaults=True)
@@ -96,7 +96,7 @@ def test_tuning_round_trip(lib):
     assert api.set_tuning(endpoint_ratio=0.25)["endpoint_ratio"] == pytest.approx(0.25)
     assert api.get_tuning()["node_path"] == api.NODES_ENDPOINTS  # unnamed field kept
     for bad in (dict(node_path=2), dict(node_path=-2), dict(endpoint_ratio=-0.1),
-                dict(endpoint_ratio=3.0), dict(local_variant=2), dict(local_variant=-1),
+                dict(endpoint_ratio=3.0), dict(local_variant=3), dict(local_variant=-1),
                 dict(lds_digit_bias=4), dict(lds_digit_bias=-4)):
         with pytest.raises(api.DbgError):
             api.set_tuning(**bad)

@@ -8,9 +8,9 @@ from paper_1003_1940_amd import api, autotune
 
 def test_candidates_cover_every_knob():
     c = autotune.candidates()
-    assert len(c) == 12
+    assert len(c) == 18
     assert {x["node_path"] for x in c} == {api.NODES_KMERS, api.NODES_ENDPOINTS}
-    assert {x["local_variant"] for x in c} == {0, 1}
+    assert {x["local_variant"] for x in c} == {0, 1, 2}
     assert {x["lds_digit_bias"] for x in c} == {-1, 0, 1}
 
 
