@@ -144,25 +144,67 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d) {
   return m;
 }
 
+// Wave64 scans and reductions through DPP lane moves inside rows of 16 lanes
+// (row_shr), then the three row totals read out to scalars; no LDS crossbar
+// traffic.  Every lane of the wave must be active.  `old` fills the lanes a
+// shift leaves without a source: the identity of the operation.
+template <int CTRL, uint32_t OLD> __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)OLD, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL, uint32_t OLD, typename T> __device__ __forceinline__ T dpp_move(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(T) == 4) {
+    return (T)dpp_u32<CTRL, OLD>((uint32_t)v);
+  } else {
+    const uint32_t lo = dpp_u32<CTRL, OLD>((uint32_t)v);
+    const uint32_t hi = dpp_u32<CTRL, OLD>((uint32_t)((uint64_t)v >> 32));
+    return (T)(((uint64_t)hi << 32) | lo);
+  }
+}
+template <typename T> __device__ __forceinline__ T read_lane(T v, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)__builtin_amdgcn_readlane((uint32_t)v, l);
+  } else {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), l);
+    return (T)(((uint64_t)hi << 32) | lo);
+  }
+}
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114,
+              DPP_ROW_SHR8 = 0x118;
+
 // Inclusive scan across a wave64.
 template <typename T> __device__ __forceinline__ T wave_inclusive_scan(T v) {
+  v += dpp_move<DPP_ROW_SHR1, 0u>(v);
+  v += dpp_move<DPP_ROW_SHR2, 0u>(v);
+  v += dpp_move<DPP_ROW_SHR4, 0u>(v);
+  v += dpp_move<DPP_ROW_SHR8, 0u>(v);
+  const T r0 = read_lane(v, 15), r1 = read_lane(v, 31), r2 = read_lane(v, 47);
   const uint32_t l = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const T t = __shfl_up(v, d, 64);
-    if (l >= (uint32_t)d) v += t;
-  }
-  return v;
+  const T add = (l >= 16 ? r0 : T(0)) + (l >= 32 ? r1 : T(0)) + (l >= 48 ? r2 : T(0));
+  return v + add;
 }
+// Reductions whose result every lane receives.
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+  v += dpp_move<DPP_ROW_SHR1, 0u>(v);
+  v += dpp_move<DPP_ROW_SHR2, 0u>(v);
+  v += dpp_move<DPP_ROW_SHR4, 0u>(v);
+  v += dpp_move<DPP_ROW_SHR8, 0u>(v);
+  return read_lane(v, 15) + read_lane(v, 31) + read_lane(v, 47) + read_lane(v, 63);
 }
 template <typename T> __device__ __forceinline__ T wave_or(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
-  return v;
+  v |= dpp_move<DPP_ROW_SHR1, 0u>(v);
+  v |= dpp_move<DPP_ROW_SHR2, 0u>(v);
+  v |= dpp_move<DPP_ROW_SHR4, 0u>(v);
+  v |= dpp_move<DPP_ROW_SHR8, 0u>(v);
+  return read_lane(v, 15) | read_lane(v, 31) | read_lane(v, 47) | read_lane(v, 63);
+}
+template <typename T> __device__ __forceinline__ T wave_and(T v) {
+  v &= dpp_move<DPP_ROW_SHR1, 0xffffffffu>(v);
+  v &= dpp_move<DPP_ROW_SHR2, 0xffffffffu>(v);
+  v &= dpp_move<DPP_ROW_SHR4, 0xffffffffu>(v);
+  v &= dpp_move<DPP_ROW_SHR8, 0xffffffffu>(v);
+  return read_lane(v, 15) & read_lane(v, 31) & read_lane(v, 47) & read_lane(v, 63);
 }
 
 // Exclusive scan of one value per thread over a workgroup of NT threads

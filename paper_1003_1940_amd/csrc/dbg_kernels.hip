@@ -637,13 +637,15 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
 
 // ---------------------------------------------------------------------------
 // Bucket planning: after a parent's 256 sub-buckets are counted, scan the counts
-// into cursors and put each sub-bucket on one of three lists.  Oversized ones
-// (more keys than the LDS sort holds) go to the next partition level, or, when
-// no digit is left (all their keys are equal), to the uniform list.  Medium
-// ones (more than half the capacity) are a batch each.  Small ones are grouped:
-// consecutive small sub-buckets whose last keys fall in the same window of
-// half the capacity form one batch, so a batch never exceeds the capacity.
-// All 256 sub-buckets are classified in parallel, one per thread.
+// into cursors and sort the sub-buckets into three kinds.  Oversized ones (more
+// keys than the LDS sort holds) go to the next partition level, or, when no
+// digit is left (all their keys are equal), to the uniform list.  The others are
+// packed into batches in key order, greedily: a sub-bucket joins the open batch
+// while the batch stays within the capacity, else it opens the next one; an
+// oversized sub-bucket closes the open batch (its keys lie in between).  Any two
+// consecutive batches of a run hold more than the capacity together, so the
+// batches of a parent number at most 2 (keys / capacity) + 1 plus one per
+// oversized sub-bucket.
 
 struct PlanArgs {
   Item *next_items;       // list receiving oversized buckets
@@ -660,60 +662,77 @@ struct PlanArgs {
   int gate;
 };
 
+constexpr uint32_t PLAN_LARGE = 0xffffffffu;
+
 struct PlanLds {
   uint64_t wsum[STREAM_NT / 64 + 1];
-  uint64_t bend[256];
+  uint64_t ex[256];         // first key of each sub-bucket (relative to the parent)
   uint64_t base[3];
-  uint8_t cls[256];
-  uint32_t win[256];
+  alignas(16) uint32_t sz[256];  // keys of each sub-bucket, PLAN_LARGE if oversized
+  uint32_t bchild[256];     // first sub-bucket of each batch
+  uint32_t bsize[256];      // keys of each batch
+  uint32_t nb;
 };
 
-enum : uint8_t { C_EMPTY = 0, C_SMALL = 1, C_MEDIUM = 2, C_LARGE = 3 };
-
 // Called by the whole workgroup (256 threads), thread d passing the count c of
-// sub-bucket d of the parent whose keys start at `off`; children live in buffer `src`; `child_level` is the digit level
-// that would split a child.
+// sub-bucket d of the parent whose keys start at `off`; children live in buffer
+// `src`; `child_level` is the digit level that would split a child.
 __device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint32_t src,
                               int child_level, uint64_t *cursor, PlanLds &s) {
   const uint32_t d = threadIdx.x;
   uint64_t total;
   const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &total);
   cursor[d] = off + ex;
-  const uint64_t half = p.local_cap / 2;
-  const uint8_t cls = c == 0 ? C_EMPTY : c <= half ? C_SMALL : c <= p.local_cap ? C_MEDIUM : C_LARGE;
-  const uint32_t win = c ? (uint32_t)((ex + c - 1) / half) : 0u;
-  s.cls[d] = cls;
-  s.win[d] = win;
-  s.bend[d] = 0;
+  const bool large = c > p.local_cap;
+  s.ex[d] = ex;
+  s.sz[d] = large ? PLAN_LARGE : (uint32_t)c;
   __syncthreads();
-  // batch starts: a medium child, or a small child whose nearest non-empty
-  // predecessor is not small or ends in another window
-  bool start = cls == C_MEDIUM;
-  if (cls == C_SMALL) {
-    int q = (int)d - 1;
-    while (q >= 0 && s.cls[q] == C_EMPTY) --q;
-    start = q < 0 || s.cls[q] != C_SMALL || s.win[q] != win;
-  }
-  const bool large = cls == C_LARGE;
-  const bool digits_left = p.bits - 8 * child_level > 0;
-  uint64_t n_start, n_large;
-  const uint64_t bid_ex = block_exclusive_scan<STREAM_NT>((uint64_t)start, s.wsum, &n_start);
-  const uint64_t lid = block_exclusive_scan<STREAM_NT>((uint64_t)large, s.wsum, &n_large);
   if (d == 0) {
-    s.base[0] = n_start ? atomicAdd((unsigned long long *)&p.ctl->n_batches, n_start) : 0;
+    const uint32_t cap = (uint32_t)p.local_cap;
+    uint32_t nb = 0, first = 0, fill = 0;  // fill = 0: no batch open
+    const uint4 *z4 = reinterpret_cast<const uint4 *>(s.sz);
+    for (uint32_t q4 = 0; q4 < 64; ++q4) {
+      const uint4 v = z4[q4];
+      const uint32_t zz[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t z = zz[i];
+        if (z == 0) continue;
+        const bool close = fill && (z == PLAN_LARGE || fill + z > cap);
+        if (close) {
+          s.bchild[nb] = first;
+          s.bsize[nb] = fill;
+          ++nb;
+          fill = 0;
+        }
+        if (z == PLAN_LARGE) continue;
+        if (fill == 0) first = 4 * q4 + (uint32_t)i;
+        fill += z;
+      }
+    }
+    if (fill) {
+      s.bchild[nb] = first;
+      s.bsize[nb] = fill;
+      ++nb;
+    }
+    s.nb = nb;
+  }
+  const bool digits_left = p.bits - 8 * child_level > 0;
+  uint64_t n_large;
+  const uint64_t lid = block_exclusive_scan<STREAM_NT>((uint64_t)large, s.wsum, &n_large);
+  // (the scan's barriers also publish nb)
+  const uint32_t nb = s.nb;
+  if (d == 0) {
+    s.base[0] = nb ? atomicAdd((unsigned long long *)&p.ctl->n_batches, (unsigned long long)nb) : 0;
     s.base[1] = n_large && digits_left
                     ? atomicAdd((unsigned long long *)p.next_count, n_large) : 0;
     s.base[2] = n_large && !digits_left
                     ? atomicAdd((unsigned long long *)&p.ctl->n_uniform, n_large) : 0;
   }
-  // batch of a small child = the last start at or before it
-  const uint32_t my_batch = (uint32_t)(bid_ex + (start ? 1 : 0)) - 1u;
-  if (cls == C_SMALL || cls == C_MEDIUM)
-    atomicMax((unsigned long long *)&s.bend[my_batch], (unsigned long long)(ex + c));
   __syncthreads();
-  if (start) {
-    const uint64_t bi = s.base[0] + bid_ex;
-    if (bi < p.batch_cap) p.batches[bi] = Batch{off + ex, (uint32_t)(s.bend[bid_ex] - ex), src};
+  if (d < nb) {
+    const uint64_t bi = s.base[0] + d;
+    if (bi < p.batch_cap) p.batches[bi] = Batch{off + s.ex[s.bchild[d]], s.bsize[d], src};
     else set_status(p.ctl, DBG_E_INTERNAL);
   }
   if (large) {
@@ -921,11 +940,7 @@ __device__ __forceinline__ int bit_length(u128 x) {
   return hi ? 128 - __clzll(hi) : (lo ? 64 - __clzll(lo) : 0);
 }
 __device__ __forceinline__ uint64_t wave_or_key(uint64_t v) { return wave_or(v); }
-__device__ __forceinline__ uint64_t wave_and_key(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v &= __shfl_xor(v, d, 64);
-  return v;
-}
+__device__ __forceinline__ uint64_t wave_and_key(uint64_t v) { return wave_and(v); }
 __device__ __forceinline__ u128 wave_and_key(u128 v) {
   const uint64_t lo = wave_and_key((uint64_t)v), hi = wave_and_key((uint64_t)(v >> 64));
   return ((u128)hi << 64) | lo;
@@ -1360,10 +1375,10 @@ template <typename S, int LPT>
 __device__ __forceinline__ void record_claims(S &s, uint32_t claimed, uint32_t ncl,
                                               const uint32_t (&hs)[LPT]) {
   const uint32_t incl = wave_inclusive_scan(ncl);
-  const uint32_t wtot = __shfl(incl, 63, 64);
+  const uint32_t wtot = read_lane(incl, 63);
   uint32_t base = 0;
   if (lane_id() == 0 && wtot) base = atomicAdd(&s.nuniq, wtot);
-  base = __shfl(base, 0, 64) + incl - ncl;
+  base = read_lane(base, 0) + incl - ncl;
 #pragma unroll
   for (int j = 0; j < LPT; ++j)
     if (claimed & (1u << j)) s.ulist[base++] = (uint16_t)hs[j];
