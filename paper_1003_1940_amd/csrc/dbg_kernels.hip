@@ -1251,8 +1251,14 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
     if (tid + (uint32_t)j * NT < nu) {
       const uint32_t b = bstart[ud[j]], e = H[ud[j]];
       if (e - b <= 64u) {
-        uint32_t r = 0;
-        for (uint32_t i = b; i < e; ++i) r += key0[i] < uk[j] ? 1u : 0u;
+        // four reads in flight per step
+        const K x = uk[j];
+        uint32_t r = 0, i = b;
+        for (; i + 4 <= e; i += 4) {
+          const K a0 = key0[i], a1 = key0[i + 1], a2 = key0[i + 2], a3 = key0[i + 3];
+          r += (a0 < x ? 1u : 0u) + (a1 < x ? 1u : 0u) + (a2 < x ? 1u : 0u) + (a3 < x ? 1u : 0u);
+        }
+        for (; i < e; ++i) r += key0[i] < x ? 1u : 0u;
         fin[j] = b + r;
       }
     }
@@ -1349,6 +1355,23 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
   __syncthreads();
 }
 
+// A batch descriptor read ahead is held in one VGPR, dword l in lane l < 4, so
+// that the compiler cannot move it into scalar registers (and wait for the load)
+// before it is used a whole batch later.  The index is clamped to the last
+// descriptor: a descriptor is only used while its index is below n.
+__device__ __forceinline__ uint32_t desc_lane_load(const Batch *batches, uint64_t i, uint64_t n) {
+  static_assert(sizeof(Batch) == 16, "four dwords: off (lo, hi), size, src");
+  const uint32_t l = lane_id();
+  uint32_t v = 0;
+  if (n && l < 4) v = reinterpret_cast<const uint32_t *>(batches + (i < n ? i : n - 1))[l];
+  return v;
+}
+__device__ __forceinline__ Batch desc_unpack(uint32_t v) {
+  const uint32_t lo = __builtin_amdgcn_readlane(v, 0), hi = __builtin_amdgcn_readlane(v, 1);
+  return Batch{((uint64_t)hi << 32) | lo, (uint32_t)__builtin_amdgcn_readlane(v, 2),
+               (uint32_t)__builtin_amdgcn_readlane(v, 3)};
+}
+
 // Keys (and weights) of a batch into registers: key e = tid + j NT.
 template <typename K, bool W, int NT, int LPT>
 __device__ __forceinline__ void load_batch(const Batch &b, const K *b0, const K *b1,
@@ -1423,7 +1446,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
   const Batch none = {0, 0, 0};
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
   load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
-  Batch nxt2 = blockIdx.x + G < n_batches ? batches[blockIdx.x + G] : none;
+  uint32_t nd2 = desc_lane_load(batches, blockIdx.x + G, n_batches);
   for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
     const Batch bt = nxt;
     const uint32_t m = bt.size;
@@ -1500,8 +1523,8 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     __syncthreads();
     // the next batch's keys load while this one is sorted (descriptors are read
     // two batches ahead)
-    nxt = nxt2;
-    nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
+    nxt = desc_unpack(nd2);
+    nd2 = desc_lane_load(batches, bi + 2 * G, n_batches);
     if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
     K kall_or = 0, kall_and = all_ones<K>();
 #pragma unroll
@@ -1561,7 +1584,7 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
   const Batch none = {0, 0, 0};
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
   load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
-  Batch nxt2 = blockIdx.x + G < n_batches ? batches[blockIdx.x + G] : none;
+  uint32_t nd2 = desc_lane_load(batches, blockIdx.x + G, n_batches);
   for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
     const Batch bt = nxt;
     const uint32_t m = bt.size;
@@ -1638,8 +1661,8 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
       record_claims(s, claimed, ncl, hs);
     }
     __syncthreads();
-    nxt = nxt2;
-    nxt2 = bi + 2 * G < n_batches ? batches[bi + 2 * G] : none;
+    nxt = desc_unpack(nd2);
+    nd2 = desc_lane_load(batches, bi + 2 * G, n_batches);
     if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
     K kall_or = 0, kall_and = all_ones<K>();
 #pragma unroll
