@@ -270,24 +270,34 @@ __device__ __forceinline__ TileRange enum_tile(const EnumArgs &a, uint64_t t) {
   return r;
 }
 
-// Word and read-base accessors: the tile's span of the packed stream and of
-// rbase is staged in LDS when it fits, otherwise read from global memory.
+// Word, read-base and read-offset accessors: the tile's span of the packed
+// stream and its reads' bases and offsets are staged in LDS when they fit,
+// otherwise read from global memory (a key's position is found at every read
+// start, so an offset read from global memory would stall the whole wave).
 constexpr uint64_t ENUM_WCAP = 1024;  // packed words staged per tile
 constexpr uint64_t ENUM_RCAP = 512;   // read bases staged per tile
 
 struct EnumLds {
   uint64_t words[ENUM_WCAP];
   uint64_t rb[ENUM_RCAP];
+  uint64_t off[ENUM_RCAP];
 };
 
+// The staged arrays are addressed through LDS-typed pointers: a generic pointer
+// chosen between LDS and global memory would compile to flat loads, whose waits
+// cover both kinds of memory traffic.
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+
 struct TileSrc {
-  const uint64_t *lw;  // LDS words [lw_base, lw_base + lw_n)
+  lds_u64 *lw;  // LDS words [lw_base, lw_base + lw_n)
   uint64_t lw_base, lw_n;
   const uint64_t *gw;
   uint64_t n_words;
-  const uint64_t *lr;  // LDS read bases [lr_base, lr_base + lr_n)
+  lds_u64 *lr;  // LDS read bases [lr_base, lr_base + lr_n)
+  lds_u64 *lo;  // LDS read offsets, same rows
   uint64_t lr_base, lr_n;
   const uint64_t *gr;
+  const uint64_t *go;
   __device__ __forceinline__ uint64_t word(uint64_t i) const {
     const uint64_t r = i - lw_base;
     if (r < lw_n) return lw[r];
@@ -296,6 +306,10 @@ struct TileSrc {
   __device__ __forceinline__ uint64_t rbase(uint64_t i) const {
     const uint64_t r = i - lr_base;
     return r < lr_n ? lr[r] : gr[i];
+  }
+  __device__ __forceinline__ uint64_t offset(uint64_t i) const {
+    const uint64_t r = i - lr_base;
+    return r < lr_n ? lo[r] : go[i];
   }
 };
 
@@ -306,8 +320,10 @@ __device__ __forceinline__ TileSrc stage_tile(const EnumArgs &a, const TileRange
   ts.gw = a.packed;
   ts.n_words = a.n_words;
   ts.gr = a.rbase;
-  ts.lw = L.words;
-  ts.lr = L.rb;
+  ts.go = a.offsets;
+  ts.lw = (lds_u64 *)L.words;
+  ts.lr = (lds_u64 *)L.rb;
+  ts.lo = (lds_u64 *)L.off;
   const uint64_t wb = a.offsets[tr.read_lo] >> 5;
   const uint64_t we = (a.offsets[tr.read_hi] + 31) >> 5;
   ts.lw_base = wb;
@@ -317,7 +333,10 @@ __device__ __forceinline__ TileSrc stage_tile(const EnumArgs &a, const TileRange
   ts.lr_n = nr <= ENUM_RCAP ? nr : 0;
   for (uint64_t i = threadIdx.x; i < ts.lw_n; i += blockDim.x)
     L.words[i] = wb + i < a.n_words ? a.packed[wb + i] : 0ull;
-  for (uint64_t i = threadIdx.x; i < ts.lr_n; i += blockDim.x) L.rb[i] = a.rbase[tr.read_lo + i];
+  for (uint64_t i = threadIdx.x; i < ts.lr_n; i += blockDim.x) {
+    L.rb[i] = a.rbase[tr.read_lo + i];
+    L.off[i] = a.offsets[tr.read_lo + i];
+  }
   __syncthreads();
   return ts;
 }
@@ -356,7 +375,7 @@ __device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, u
   }
   uint64_t i = lo;
   uint64_t next = ts.rbase(i + 1);
-  uint64_t p = a.offsets[i] + (g0 - ts.rbase(i));
+  uint64_t p = ts.offset(i) + (g0 - ts.rbase(i));
   const int len = a.len;
   const K mask = low_mask<K>(2 * len);
   const int top = 2 * len - 2;
@@ -373,7 +392,7 @@ __device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, u
             ++i;
             next = ts.rbase(i + 1);
           } while (next == g);
-          p = a.offsets[i];
+          p = ts.offset(i);
           fw = extract_key(ts, p, len, K());
           rc = revcomp(fw, len);
         } else {
