@@ -270,50 +270,42 @@ __device__ __forceinline__ TileRange enum_tile(const EnumArgs &a, uint64_t t) {
   return r;
 }
 
-// Word, read-base and read-offset accessors: the tile's span of the packed
-// stream and its reads' bases and offsets are staged in LDS when they fit,
-// otherwise read from global memory (a key's position is found at every read
-// start, so an offset read from global memory would stall the whole wave).
-constexpr uint64_t ENUM_WCAP = 1024;  // packed words staged per tile
-constexpr uint64_t ENUM_RCAP = 512;   // read bases staged per tile
+// A tile's keys are enumerated from LDS when its span of the packed stream (plus
+// two words, so that a key's last word read never needs a bounds check) and its
+// reads fit: positions are then 32-bit offsets from the first staged word and
+// key indices 32-bit offsets from the first read's first key.  Tiles that do not
+// fit (very long reads, or very many reads shorter than a key) read global memory.
+constexpr uint32_t ENUM_WCAP = 1024;  // packed words staged per tile
+constexpr uint32_t ENUM_RCAP = 1024;  // read rows staged per tile
+
+// The staged arrays are addressed through LDS-typed pointers, so that every access
+// compiles to an LDS instruction.
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 
 struct EnumLds {
-  uint64_t words[ENUM_WCAP];
-  uint64_t rb[ENUM_RCAP];
-  uint64_t off[ENUM_RCAP];
+  uint64_t words[ENUM_WCAP + 2];
+  uint32_t rb[ENUM_RCAP];   // first key of each read, from the tile's first read's
+  uint32_t off[ENUM_RCAP];  // first base of each read, from the first staged word's
 };
-
-// The staged arrays are addressed through LDS-typed pointers: a generic pointer
-// chosen between LDS and global memory would compile to flat loads, whose waits
-// cover both kinds of memory traffic.
-typedef __attribute__((address_space(3))) const uint64_t lds_u64;
 
 struct TileSrc {
-  lds_u64 *lw;  // LDS words [lw_base, lw_base + lw_n)
-  uint64_t lw_base, lw_n;
-  const uint64_t *gw;
+  bool fast;  // staged in LDS (uniform over the workgroup)
+  // staged tile
+  lds_u64 *lw;
+  lds_u32 *lrb, *loff;
+  uint64_t g_base;  // key index of rb[0]
+  uint32_t nr;      // read rows staged (read_lo .. read_hi)
+  // global memory
+  const uint64_t *gw, *gr, *go;
   uint64_t n_words;
-  lds_u64 *lr;  // LDS read bases [lr_base, lr_base + lr_n)
-  lds_u64 *lo;  // LDS read offsets, same rows
-  uint64_t lr_base, lr_n;
-  const uint64_t *gr;
-  const uint64_t *go;
-  __device__ __forceinline__ uint64_t word(uint64_t i) const {
-    const uint64_t r = i - lw_base;
-    if (r < lw_n) return lw[r];
-    return i < n_words ? gw[i] : 0ull;
-  }
-  __device__ __forceinline__ uint64_t rbase(uint64_t i) const {
-    const uint64_t r = i - lr_base;
-    return r < lr_n ? lr[r] : gr[i];
-  }
-  __device__ __forceinline__ uint64_t offset(uint64_t i) const {
-    const uint64_t r = i - lr_base;
-    return r < lr_n ? lo[r] : go[i];
-  }
+  __device__ __forceinline__ uint64_t word(uint64_t i) const { return i < n_words ? gw[i] : 0ull; }
+  __device__ __forceinline__ uint64_t rbase(uint64_t i) const { return gr[i]; }
+  __device__ __forceinline__ uint64_t offset(uint64_t i) const { return go[i]; }
 };
 
-// Stage a tile's words and read bases (whole workgroup; contains a barrier).
+// Stage a tile's words and reads when they fit (whole workgroup; contains a
+// barrier).
 __device__ __forceinline__ TileSrc stage_tile(const EnumArgs &a, const TileRange &tr,
                                               EnumLds &L) {
   TileSrc ts;
@@ -322,20 +314,23 @@ __device__ __forceinline__ TileSrc stage_tile(const EnumArgs &a, const TileRange
   ts.gr = a.rbase;
   ts.go = a.offsets;
   ts.lw = (lds_u64 *)L.words;
-  ts.lr = (lds_u64 *)L.rb;
-  ts.lo = (lds_u64 *)L.off;
+  ts.lrb = (lds_u32 *)L.rb;
+  ts.loff = (lds_u32 *)L.off;
   const uint64_t wb = a.offsets[tr.read_lo] >> 5;
   const uint64_t we = (a.offsets[tr.read_hi] + 31) >> 5;
-  ts.lw_base = wb;
-  ts.lw_n = we - wb <= ENUM_WCAP ? we - wb : 0;
-  ts.lr_base = tr.read_lo;
+  const uint64_t nw = we - wb + 2;
   const uint64_t nr = tr.read_hi - tr.read_lo + 1;
-  ts.lr_n = nr <= ENUM_RCAP ? nr : 0;
-  for (uint64_t i = threadIdx.x; i < ts.lw_n; i += blockDim.x)
-    L.words[i] = wb + i < a.n_words ? a.packed[wb + i] : 0ull;
-  for (uint64_t i = threadIdx.x; i < ts.lr_n; i += blockDim.x) {
-    L.rb[i] = a.rbase[tr.read_lo + i];
-    L.off[i] = a.offsets[tr.read_lo + i];
+  ts.fast = nw <= ENUM_WCAP + 2 && nr <= ENUM_RCAP;
+  ts.nr = (uint32_t)nr;
+  ts.g_base = a.rbase[tr.read_lo];
+  if (ts.fast) {
+    for (uint32_t i = threadIdx.x; i < (uint32_t)nw; i += blockDim.x)
+      L.words[i] = wb + i < a.n_words ? a.packed[wb + i] : 0ull;
+    const uint64_t p0 = wb << 5;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)nr; i += blockDim.x) {
+      L.rb[i] = (uint32_t)(a.rbase[tr.read_lo + i] - ts.g_base);
+      L.off[i] = (uint32_t)(a.offsets[tr.read_lo + i] - p0);
+    }
   }
   __syncthreads();
   return ts;
@@ -357,14 +352,82 @@ __device__ __forceinline__ u128 extract_key(const TileSrc &ts, uint64_t p, int l
   const uint64_t lo = o ? ((w1 << o) | (w2 >> (64 - o))) : w1;
   return shr<u128>(((u128)hi << 64) | (u128)lo, 128 - 2 * len);
 }
+// The same from the staged words (P: bases from the first staged word).
+__device__ __forceinline__ uint64_t extract_staged(lds_u64 *w, uint32_t P, int len, uint64_t) {
+  const uint32_t wi = P >> 5;
+  const int o = (int)(P & 31) * 2;
+  const uint64_t w0 = w[wi], w1 = w[wi + 1];
+  const uint64_t v = o ? ((w0 << o) | (w1 >> (64 - o))) : w0;
+  return len == 32 ? v : (v >> (64 - 2 * len));
+}
+__device__ __forceinline__ u128 extract_staged(lds_u64 *w, uint32_t P, int len, u128) {
+  const uint32_t wi = P >> 5;
+  const int o = (int)(P & 31) * 2;
+  const uint64_t w0 = w[wi], w1 = w[wi + 1], w2 = w[wi + 2];
+  const uint64_t hi = o ? ((w0 << o) | (w1 >> (64 - o))) : w0;
+  const uint64_t lo = o ? ((w1 << o) | (w2 >> (64 - o))) : w1;
+  return shr<u128>(((u128)hi << 64) | (u128)lo, 128 - 2 * len);
+}
 
 // Keys g0, g0+1, ... (< g_end, at most KPT) into out[]: the canonical key at each
 // position, rolling the forward and reverse-complement registers by one base
 // within a read and re-seeding them at each read start.  Returns the count.
+// Staged tile: 32-bit positions and LDS reads only.
 template <typename K, int KPT>
-__device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, uint64_t g0,
-                                         uint64_t g_end, uint64_t read_lo, uint64_t read_hi,
-                                         K (&out)[KPT]) {
+__device__ __forceinline__ int enum_keys_staged(const EnumArgs &a, const TileSrc &ts, uint64_t g0,
+                                                uint64_t g_end, K (&out)[KPT]) {
+  if (g0 >= g_end) return 0;
+  const uint32_t gl0 = (uint32_t)(g0 - ts.g_base), gle = (uint32_t)(g_end - ts.g_base);
+  // local read i with rb[i] <= gl0 < rb[i+1] (rb[0] = 0 and rb[nr-1] >= the tile's end)
+  uint32_t lo = 0, hi = ts.nr - 1;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (ts.lrb[mid] <= gl0) lo = mid;
+    else hi = mid;
+  }
+  uint32_t i = lo;
+  uint32_t next = ts.lrb[i + 1];
+  uint32_t P = ts.loff[i] + (gl0 - ts.lrb[i]);
+  const int len = a.len;
+  const K mask = low_mask<K>(2 * len);
+  const int top = 2 * len - 2;
+  K fw = extract_staged(ts.lw, P, len, K());
+  K rc = revcomp(fw, len);
+  int n = 0;
+  uint32_t g = gl0;
+#pragma unroll
+  for (int r = 0; r < KPT; ++r) {
+    if (g < gle) {
+      if (r > 0) {
+        if (g == next) {
+          do {
+            ++i;
+            next = ts.lrb[i + 1];
+          } while (next == g);
+          P = ts.loff[i];
+          fw = extract_staged(ts.lw, P, len, K());
+          rc = revcomp(fw, len);
+        } else {
+          const uint32_t q = P + (uint32_t)len;
+          const uint32_t c = (uint32_t)(ts.lw[q >> 5] >> (62 - 2 * (int)(q & 31))) & 3u;
+          fw = ((fw << 2) | (K)c) & mask;
+          rc = (rc >> 2) | ((K)(3u - c) << top);
+          ++P;
+        }
+      }
+      out[r] = rc < fw ? rc : fw;
+      ++n;
+      ++g;
+    }
+  }
+  return n;
+}
+
+// Tiles that do not fit in LDS: the same from global memory.
+template <typename K, int KPT>
+__device__ __forceinline__ int enum_keys_global(const EnumArgs &a, const TileSrc &ts, uint64_t g0,
+                                                uint64_t g_end, uint64_t read_lo,
+                                                uint64_t read_hi, K (&out)[KPT]) {
   if (g0 >= g_end) return 0;
   // read i with rbase[i] <= g0 < rbase[i+1]
   uint64_t lo = read_lo, hi = read_hi;  // rbase[lo] <= g0 < rbase[hi]
@@ -409,6 +472,14 @@ __device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, u
     }
   }
   return n;
+}
+
+template <typename K, int KPT>
+__device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, uint64_t g0,
+                                         uint64_t g_end, uint64_t read_lo, uint64_t read_hi,
+                                         K (&out)[KPT]) {
+  if (ts.fast) return enum_keys_staged<K, KPT>(a, ts, g0, g_end, out);
+  return enum_keys_global<K, KPT>(a, ts, g0, g_end, read_lo, read_hi, out);
 }
 
 // SL: the build is a key-space slice (keys outside [pfx_lo, pfx_hi) are dropped);
