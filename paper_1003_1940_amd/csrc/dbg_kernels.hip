@@ -93,6 +93,19 @@ __global__ void k_fill_u64(uint64_t *a, uint64_t n, uint64_t v) {
     a[i] = v;
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn.  The scatter kernels give
+// each XCD one contiguous eighth of the tiles, so that neighbouring tiles, whose
+// output runs share cache lines at their ends, are written through the same L2.
+constexpr uint32_t N_XCD = 8;
+// Workgroup b of a one-tile-per-workgroup grid (a multiple of 8 workgroups, at
+// least n): its tile, or n if it has none.
+__device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t n) {
+  const uint64_t per = (n + N_XCD - 1) / N_XCD;
+  const uint64_t i = b / N_XCD;
+  const uint64_t t = (b % N_XCD) * per + i;
+  return i < per && t < n ? t : n;
+}
+
 // ---------------------------------------------------------------------------
 // 1. Per-read key counts c_i = max(0, L_i - len + 1) and their prefix rbase.
 
@@ -701,8 +714,10 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
   // the staged words share LDS with the partition's key buffer: partition_tile
   // passes a barrier before it writes keys, after every thread has enumerated
   __shared__ PartLds<K> s;
-  const uint64_t t = blockIdx.x;
-  if (ctl->status || gated_off(ctl, a.gate) || t >= ctl->n_tiles) return;
+  if (ctl->status || gated_off(ctl, a.gate)) return;
+  const uint64_t nt = ctl->n_tiles;
+  const uint64_t t = xcd_tile(blockIdx.x, nt);
+  if (t >= nt) return;
   const TileRange tr = enum_tile(a, t);
   const TileSrc ts = stage_tile(a, tr, s.stage);
   K keys[STREAM_KPT];
@@ -982,7 +997,12 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0,
   __shared__ PartLds<K, W> s;
   if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t n_tiles = *a.n_tiles_p, n_items = *a.n_items_p;
-  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  // this XCD's eighth of the tiles, strided over its workgroups (gridDim.x is a
+  // multiple of 8)
+  const uint64_t per = (n_tiles + N_XCD - 1) / N_XCD;
+  const uint64_t x0 = (blockIdx.x % N_XCD) * per;
+  const uint64_t x1 = x0 + per < n_tiles ? x0 + per : n_tiles;
+  for (uint64_t t = x0 + blockIdx.x / N_XCD; t < x1; t += gridDim.x / N_XCD) {
     const uint64_t ii = find_item(a.items, n_items, t);
     const Item it = a.items[ii];
     const uint64_t start = it.off + (t - it.tbase) * TILE;
@@ -2087,6 +2107,11 @@ static void launch_local_sort(unsigned grid, hipStream_t st, const Batch *batche
                        batches, n_batches, x0, x1, wt0, wt1, bits, ctl, gate, bias);
 }
 
+// A grid rounded up to a multiple of the XCD count.
+static inline uint64_t xcd_grid(uint64_t n) {
+  return (n + N_XCD - 1) / N_XCD * N_XCD;
+}
+
 static inline unsigned grid_for(uint64_t n, uint64_t per, uint64_t cap) {
   uint64_t g = (n + per - 1) / per;
   if (g < 1) g = 1;
@@ -2196,7 +2221,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
               uniform, L.item_cap, ctl, cap_u, bits, g0};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
-  const unsigned level_grid = grid_for(L.max_tiles + L.item_cap, 1, 8192);
+  const unsigned level_grid = (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, 8192));
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
   LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], thist, cursor, wt0,
                 wt1, bits, 0, 1};
@@ -2214,10 +2239,10 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   }
   stage(ev + 3, st);
   if (sliced)
-    hipLaunchKernelGGL((k_enum_scatter<K, true>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0,
+    hipLaunchKernelGGL((k_enum_scatter<K, true>), dim3((unsigned)xcd_grid(L.max_tiles)), dim3(STREAM_NT), 0,
                        st, ea, cursor0, thist, x0, ctl);
   else
-    hipLaunchKernelGGL((k_enum_scatter<K, false>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0,
+    hipLaunchKernelGGL((k_enum_scatter<K, false>), dim3((unsigned)xcd_grid(L.max_tiles)), dim3(STREAM_NT), 0,
                        st, ea, cursor0, thist, x0, ctl);
   if (two_routes)
     hipLaunchKernelGGL((k_level_scatter<K, true>), dim3(level_grid), dim3(STREAM_NT), 0, st, la0,
