@@ -1962,12 +1962,19 @@ constexpr int EMIT_WNT = 256;
 template <typename K, bool EDGES>
 __global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
                                                          const uint64_t *tile_base, const K *b0,
-                                                         const K *b1, OutArgs o, const Ctl *ctl) {
+                                                         const K *b1, OutArgs o, uint64_t n_tiles,
+                                                         const Ctl *ctl) {
   __shared__ uint32_t wpre[EMIT_NT + 1];  // marked positions before each word of the tile
   __shared__ uint32_t wbits[EMIT_NT];
   __shared__ uint64_t wsum[EMIT_WNT / 64 + 1];
   if (ctl->status) return;
-  const uint64_t w0 = blockIdx.x * (uint64_t)EMIT_NT;
+  // tiles holding key positions (the endpoint records of a node table, or the
+  // table's keys), each XCD a contiguous eighth
+  const uint64_t used = !EDGES && ctl->node_path == 1 ? ctl->n_records : ctl->n_keys;
+  const uint64_t nt_used = (used + TILE - 1) / TILE < n_tiles ? (used + TILE - 1) / TILE : n_tiles;
+  const uint64_t tile = xcd_tile(blockIdx.x, nt_used);
+  if (tile >= nt_used) return;
+  const uint64_t w0 = tile * (uint64_t)EMIT_NT;
   const uint32_t word = threadIdx.x < (uint32_t)EMIT_NT ? bits[w0 + threadIdx.x] : 0u;
   uint64_t tot;
   const uint32_t ex = (uint32_t)block_exclusive_scan<EMIT_WNT>((uint64_t)__popc(word), wsum, &tot);
@@ -1977,7 +1984,7 @@ __global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
   }
   if (threadIdx.x == 0) wpre[EMIT_NT] = (uint32_t)tot;
   __syncthreads();
-  const uint64_t base = tile_base[blockIdx.x];
+  const uint64_t base = tile_base[tile];
   for (uint32_t i = threadIdx.x; i < (uint32_t)tot; i += EMIT_WNT) {
     uint32_t lo = 0, hi = EMIT_NT;  // the last word w with wpre[w] <= i
     while (hi - lo > 1) {
@@ -2323,15 +2330,15 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     oa.count = A.edges.mult;
     oa.capacity = capacity = A.edges.capacity;
     set_rows = A.edge_set_offsets;
-    hipLaunchKernelGGL((k_emit_write<K, true>), dim3((unsigned)L.rle_tiles), dim3(EMIT_WNT), 0, st,
-                       runbits, rle_heads, x0, x1, oa, ctl);
+    hipLaunchKernelGGL((k_emit_write<K, true>), dim3((unsigned)xcd_grid(L.rle_tiles)),
+                       dim3(EMIT_WNT), 0, st, runbits, rle_heads, x0, x1, oa, L.rle_tiles, ctl);
   } else {
     oa.kmer = A.nodes.kmer;
     oa.count = A.nodes.count;
     oa.capacity = capacity = A.nodes.capacity;
     set_rows = A.node_set_offsets;
-    hipLaunchKernelGGL((k_emit_write<K, false>), dim3((unsigned)L.rle_tiles), dim3(EMIT_WNT), 0, st,
-                       runbits, rle_heads, x0, x1, oa, ctl);
+    hipLaunchKernelGGL((k_emit_write<K, false>), dim3((unsigned)xcd_grid(L.rle_tiles)),
+                       dim3(EMIT_WNT), 0, st, runbits, rle_heads, x0, x1, oa, L.rle_tiles, ctl);
   }
   stage(ev + 8, st);
   hipLaunchKernelGGL(k_set_rows, dim3(grid_for(S + 1, 256, 1u << 30)), dim3(256), 0, st, runbits,
