@@ -1282,6 +1282,24 @@ __device__ __forceinline__ void mark_positions(uint32_t *bits, uint64_t off, uin
   }
 }
 
+// The batch's distinct keys, sorted in buffer 0, replace its first positions in
+// b0, their counts go to the same positions of b1, and the bitmap marks those
+// positions.  Reads LDS only.
+template <typename S, bool W>
+__device__ __forceinline__ void write_batch(S &s, const Batch &bt, uint32_t nu,
+                                            typename S::Key *b0, typename S::Key *b1,
+                                            uint32_t *bits) {
+  using K = typename S::Key;
+  using CT = typename S::CT;
+  const K *key0 = s.k0();
+  const CT *cnt0 = s.c0();
+  for (uint32_t u = threadIdx.x; u < nu; u += S::NT) {
+    b0[bt.off + u] = key0[u];
+    b1[bt.off + u] = (K)((uint32_t)cnt0[u] >> (W ? 1 : 0));
+  }
+  mark_positions(bits, bt.off, bt.size, nu);
+}
+
 // After duplicates are merged: the batch's nu distinct keys and counts are in
 // registers (uk, uc: key u = tid + j NT), hb is the highest bit in which the
 // batch's keys differ.  Partition them by a digit of about log2(nu) bits just
@@ -1289,9 +1307,11 @@ __device__ __forceinline__ void mark_positions(uint32_t *bits, uint64_t off, uin
 // against the others, refine the rare larger pieces, then write the sorted
 // distinct keys over the batch's first positions of b0, their counts (halved for
 // weighted records) to the same positions of b1, and mark those positions in the
-// bitmap.  Ends with a barrier.  The caller must have passed a barrier after its
-// last read of the LDS the buffers overwrite.
-template <typename S, bool W, int UPT>
+// bitmap (write_batch).  Ends with a barrier.  The caller must have passed a
+// barrier after its last read of the LDS the buffers overwrite.  DEFER: the
+// sorted keys are left in buffer 0 for the caller to write out later (every
+// thread has passed a barrier since they were placed).
+template <typename S, bool W, int UPT, bool DEFER = false>
 __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[UPT],
                                              const uint32_t (&uc)[UPT], uint32_t nu, int hb,
                                              int dw_bias, const Batch &bt,
@@ -1454,15 +1474,10 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
     cur ^= 1;
     __syncthreads();
   }
-  // the batch's distinct keys, sorted, replace its first positions in buffer 0,
-  // their counts go to the same positions of buffer 1, and the bitmap marks
-  // those positions
-  for (uint32_t u = tid; u < nu; u += NT) {
-    b0[bt.off + u] = key0[u];
-    b1[bt.off + u] = (K)((uint32_t)cnt0[u] >> (W ? 1 : 0));
+  if (!DEFER) {
+    write_batch<S, W>(s, bt, nu, b0, b1, bits);
+    __syncthreads();
   }
-  mark_positions(bits, bt.off, bt.size, nu);
-  __syncthreads();
 }
 
 // A batch descriptor read ahead is held in one VGPR, dword l in lane l < 4, so
@@ -1692,6 +1707,7 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
   __syncthreads();
   uint32_t prev_nu = 0;  // distinct keys of the previous batch, left in buffer 0
   const Batch none = {0, 0, 0};
+  Batch prev = none;  // the previous batch: written out once this batch's keys are in
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
   load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
   uint32_t nd2 = desc_lane_load(batches, blockIdx.x + G, n_batches);
@@ -1716,7 +1732,11 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
       s.wor[w] = kor;
       s.wand[w] = kand;
     }
-    if (s.dirty) {  // uniform: read after the previous batch's final barrier
+    // the previous batch's output, issued only now: the wait for this batch's
+    // keys (above) would otherwise also wait for these stores
+    if (bi != blockIdx.x) write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
+    __syncthreads();  // read out before the region is cleared
+    if (s.dirty) {  // uniform: set before the previous batch's last barrier
       uint4 *r4 = reinterpret_cast<uint4 *>(s.r);
       constexpr uint32_t nkey4 = (uint32_t)SLOTS * 8 / 16, ncnt4 = (uint32_t)SLOTS * 4 / 16;
       const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u), zeros = make_uint4(0u, 0u, 0u, 0u);
@@ -1798,9 +1818,11 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
         tcnt[q] = 0;
       }
     }
-    finish_batch<S, W, LPT>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
+    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
     prev_nu = nu;
+    prev = bt;
   }
+  if (blockIdx.x < n_batches) write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
 }
 
 // Oversized buckets whose digits are exhausted hold one key repeated: one
