@@ -1897,42 +1897,56 @@ __global__ void k_node_path(Ctl *ctl, uint64_t n_reads, uint64_t n_sets, int mod
   }
 }
 
+// The records, written tile by tile (4096 records, the tiles of the level-0
+// partition that follows), with each tile's counts of the top digit: the row
+// that partition's tile mode reads, so the records are not read back to count
+// them.  Record 2j and 2j+1: the endpoints u and v of distinct edge j with its
+// multiplicity; record 2 ne + 2i and 2 ne + 2i + 1: the first and last k-mer of
+// read i with weight 1 (weight 0 on the first edge's u for reads shorter than k).
 template <typename K>
-__global__ void k_rec_edges(const K *u, const K *v, const uint32_t *mult, K *keys,
-                            uint32_t *wts, const Ctl *ctl) {
+__global__ __launch_bounds__(STREAM_NT) void k_records(const K *u, const K *v,
+                                                       const uint32_t *mult,
+                                                       const uint64_t *packed, uint64_t n_words,
+                                                       const uint64_t *offsets, int k, int bits,
+                                                       K *keys, uint32_t *wts, uint32_t *thist,
+                                                       const Ctl *ctl) {
+  __shared__ uint32_t h[256];
   if (ctl->status || ctl->node_path != 1) return;
-  const uint64_t ne = ctl->n_edges;
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < ne;
-       j += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t m = mult[j];
-    keys[2 * j] = u[j];
-    keys[2 * j + 1] = v[j];
-    wts[2 * j] = m;
-    wts[2 * j + 1] = m;
-  }
-}
-
-template <typename K>
-__global__ void k_rec_ends(const uint64_t *packed, uint64_t n_words, const uint64_t *offsets,
-                           uint64_t n_reads, int k, const K *u, K *keys, uint32_t *wts,
-                           const Ctl *ctl) {
-  if (ctl->status || ctl->node_path != 1) return;
-  const uint64_t base = 2 * ctl->n_edges;
+  const uint64_t ne = ctl->n_edges, n_rec = ctl->n_records;
+  const uint64_t n_tiles = (n_rec + TILE - 1) / TILE;
   const K filler = u[0];
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_reads;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t a = offsets[i], b = offsets[i + 1];
-    K first = filler, last = filler;
-    uint32_t w = 0;
-    if (b >= a && b - a >= (uint64_t)k) {
-      first = canonical<K>(extract_bases(packed, n_words, a, k, K(0)), k);
-      last = canonical<K>(extract_bases(packed, n_words, b - (uint64_t)k, k, K(0)), k);
-      w = 1;
+  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    h[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < STREAM_KPT; ++j) {
+      const uint64_t r = t * TILE + threadIdx.x + (uint64_t)j * STREAM_NT;
+      if (r < n_rec) {
+        K key;
+        uint32_t w;
+        if (r < 2 * ne) {
+          const uint64_t e = r >> 1;
+          key = (r & 1) ? v[e] : u[e];
+          w = mult[e];
+        } else {
+          const uint64_t i = (r - 2 * ne) >> 1;
+          const uint64_t a = offsets[i], b = offsets[i + 1];
+          key = filler;
+          w = 0;
+          if (b >= a && b - a >= (uint64_t)k) {
+            const uint64_t p = ((r - 2 * ne) & 1) ? b - (uint64_t)k : a;
+            key = canonical<K>(extract_bases(packed, n_words, p, k, K(0)), k);
+            w = 1;
+          }
+        }
+        keys[r] = key;
+        wts[r] = w;
+        atomicAdd(&h[msd_digit(key, bits, 0)], 1u);
+      }
     }
-    keys[base + 2 * i] = first;
-    keys[base + 2 * i + 1] = last;
-    wts[base + 2 * i] = w;
-    wts[base + 2 * i + 1] = w;
+    __syncthreads();
+    thist[t * 256 + threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
   }
 }
 
@@ -2223,10 +2237,10 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                        st, ea, thist, ctl);
   if (two_routes) {
     const K *eu = static_cast<const K *>(A.edges.u);
-    hipLaunchKernelGGL(k_rec_edges<K>, dim3(grid_for(A.edges.capacity, 256, 8192)), dim3(256), 0,
-                       st, eu, static_cast<const K *>(A.edges.v), A.edges.mult, x0, wt0, ctl);
-    hipLaunchKernelGGL(k_rec_ends<K>, dim3(grid_for(A.n_reads, 256, 8192)), dim3(256), 0, st,
-                       A.packed, n_words, A.read_offsets, A.n_reads, A.k, eu, x0, wt0, ctl);
+    const uint64_t rec_tiles = (2 * A.edges.capacity + 2 * A.n_reads + TILE - 1) / TILE;
+    hipLaunchKernelGGL(k_records<K>, dim3(grid_for(rec_tiles, 1, 8192)), dim3(STREAM_NT), 0, st,
+                       eu, static_cast<const K *>(A.edges.v), A.edges.mult, A.packed, n_words,
+                       A.read_offsets, A.k, bits, x0, wt0, thist, ctl);
   }
   stage(ev + 2, st);
   const unsigned col_chunks = (unsigned)((L.max_tiles + COL_CHUNK - 1) / COL_CHUNK);
@@ -2258,8 +2272,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, st, ctl, items[0], hist[0]);
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[0], &ctl->items[0],
                        &ctl->level_tiles[0], &ctl->items[1], ctl, 1);
-    hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la0, x0, x1,
-                       ctl);
+    // (the records' tile rows were written by k_records)
     level_prefix(&ctl->level_tiles[0], 1);
     PlanArgs pw{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
                 uniform, L.item_cap, ctl, cap_w, bits, 1};
