@@ -107,6 +107,30 @@ def test_every_start_offset_and_ragged_lengths():
         compare_with_oracle(b, o, k, label="ragged 0..199")
 
 
+def test_tiles_beyond_lds_staging():
+    """Enumeration tiles that span more reads (1,024) or more bases (about 32,000)
+    than a tile stages in LDS take the global-memory path; the same reads built
+    with a few keys per read, and with keyless reads between keyed ones."""
+    rng = np.random.default_rng(12)
+
+    def rand(n):
+        return "".join("ACGT"[c] for c in rng.integers(0, 4, n))
+
+    for k in (31, 33):
+        # one (k+1)-mer per read: a 4,096-key edge tile spans 4,096 reads
+        reads = [rand(k + 1) for _ in range(9000)]
+        b, o = _rs(reads)
+        compare_with_oracle(b, o, k, label=f"reads of k+1 bases, k={k}")
+        # five keys per keyed read, 40 keyless reads of k-1 bases after each: a
+        # tile spans about 40,000 reads and more than 1M bases
+        reads = []
+        for _ in range(1500):
+            reads.append(rand(k + 5))
+            reads.extend(rand(k - 1) for _ in range(40))
+        b, o = _rs(reads)
+        compare_with_oracle(b, o, k, label=f"keyless reads between keyed ones, k={k}")
+
+
 def test_no_keys_and_empty():
     b, o = _rs(["ACG", "AC", ""])
     compare_with_oracle(b, o, 31, label="all reads shorter than k")
