@@ -1569,28 +1569,41 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
   }
   __syncthreads();
   const Batch none = {0, 0, 0};
+  Batch prev = none;  // the previous batch: written out once this batch's keys are in
+  uint32_t prev_nu = 0;
   Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
   load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
   uint32_t nd2 = desc_lane_load(batches, blockIdx.x + G, n_batches);
   for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
     const Batch bt = nxt;
     const uint32_t m = bt.size;
-    // 1. stage (and find the bits in which the batch's keys differ: OR ^ AND)
+    // 1. the bits in which the batch's keys differ (OR ^ AND; the first use of
+    //    the keys, so the wait for them comes here)
     K kor = 0, kand = all_ones<K>();
 #pragma unroll
-    for (int j = 0; j < LPT; ++j) {
-      const uint32_t e = tid + (uint32_t)j * NT;
-      if (e < m) {
-        s.key0[e] = pre[j];
+    for (int j = 0; j < LPT; ++j)
+      if (tid + (uint32_t)j * NT < m) {
         kor |= pre[j];
         kand &= pre[j];
       }
-    }
     kor = wave_or_key(kor);
     kand = wave_and_key(kand);
     if (lane == 0) {
       s.wor[w] = kor;
       s.wand[w] = kand;
+    }
+    // the previous batch's output, issued only now (the wait for this batch's
+    // keys would otherwise also wait for these stores) and read out of buffer 0
+    // before the keys are staged over it
+    if (bi != blockIdx.x) {
+      write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
+      __syncthreads();
+    }
+    // stage the keys
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      const uint32_t e = tid + (uint32_t)j * NT;
+      if (e < m) s.key0[e] = pre[j];
     }
     if (s.dirty) {  // uniform: read after the previous batch's final barrier
       for (uint32_t q = tid; q < (uint32_t)SLOTS; q += NT) {
@@ -1676,8 +1689,11 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
         tcnt[q] = 0;
       }
     }
-    finish_batch<S, W, LPT>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
+    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
+    prev = bt;
+    prev_nu = nu;
   }
+  if (blockIdx.x < n_batches) write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
 }
 
 template <bool W, int V>
