@@ -647,62 +647,101 @@ __global__ __launch_bounds__(256) void k_col_apply(uint32_t *thist, const uint32
 // digit-contiguously in LDS, then write each digit run with consecutive threads
 // on consecutive addresses.  `cursor` points at the 256 bucket cursors of the
 // parent.  Every thread of the workgroup must call it.
-template <typename K, bool W = false>
+template <typename K, bool W = false, int HV = 1>
 struct PartLds {
+  // HV = 2: the tile passes through LDS in two halves (half the LDS, so twice
+  // the workgroups per CU; the runs of a digit are written in two pieces)
+  static constexpr int HALVES = HV;
   union {
-    K keys[TILE];
+    K keys[TILE / HALVES];
     EnumLds stage;  // the enumeration's staged words, dead once its keys are in registers
   };
-  uint32_t wts[W ? TILE : 1];  // record weights (W), moved with their keys
+  uint32_t wts[W ? TILE / HALVES : 1];  // record weights (W), moved with their keys
   uint64_t gbase[256];
   uint32_t cnt[256];
+  uint32_t cnt0[HALVES > 1 ? 256 : 1];  // keys of each digit in the first half
   uint64_t wsum[STREAM_NT / 64 + 1];
 };
 
-template <typename K, bool W = false>
+template <typename K, bool W = false, int HV = 1>
 __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
                                                const uint32_t (&wts)[STREAM_KPT], int n, int bits,
                                                int level, uint64_t *cursor, uint64_t my_base,
-                                               K *dst, uint32_t *dstw, PartLds<K, W> &s,
+                                               K *dst, uint32_t *dstw, PartLds<K, W, HV> &s,
                                                uint32_t valid = 0xffffffffu) {
   // cursor != null: reserve each digit's range with one atomic on cursor[d];
   // otherwise thread d already holds its digit's destination start in my_base.
+  constexpr int H = HV;
   const uint32_t tid = threadIdx.x;
   uint32_t dig[STREAM_KPT];
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r) dig[r] = r < n ? msd_digit(keys[r], bits, level) : 0u;
   s.cnt[tid] = 0;
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < STREAM_KPT; ++r)
-    if (r < n && ((valid >> r) & 1u)) atomicAdd(&s.cnt[dig[r]], 1u);
-  __syncthreads();
-  const uint64_t c = s.cnt[tid];
-  uint64_t m;
-  const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &m);
-  if (cursor)
-    s.gbase[tid] =
-        c ? (uint64_t)atomicAdd((unsigned long long *)&cursor[tid], (unsigned long long)c) - ex
-          : 0;
-  else
-    s.gbase[tid] = my_base - ex;
-  s.cnt[tid] = (uint32_t)ex;
+  if (H > 1) s.cnt0[tid] = 0;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r)
     if (r < n && ((valid >> r) & 1u)) {
-      const uint32_t q = atomicAdd(&s.cnt[dig[r]], 1u);
-      s.keys[q] = keys[r];
-      if (W) s.wts[q] = wts[r];
+      atomicAdd(&s.cnt[dig[r]], 1u);
+      if (H > 1 && r < STREAM_KPT / 2) atomicAdd(&s.cnt0[dig[r]], 1u);
     }
   __syncthreads();
-  for (uint32_t idx = tid; idx < (uint32_t)m; idx += STREAM_NT) {
-    const K key = s.keys[idx];
-    const uint64_t o = s.gbase[msd_digit(key, bits, level)] + idx;
-    dst[o] = key;
-    if (W) dstw[o] = s.wts[idx];
+  const uint64_t c = s.cnt[tid];
+  uint64_t m;
+  const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &m);
+  // destination of the first key of digit tid
+  const uint64_t base =
+      cursor ? (c ? (uint64_t)atomicAdd((unsigned long long *)&cursor[tid], (unsigned long long)c)
+                  : 0)
+             : my_base;
+  if (H == 1) {
+    s.gbase[tid] = base - ex;
+    s.cnt[tid] = (uint32_t)ex;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < STREAM_KPT; ++r)
+      if (r < n && ((valid >> r) & 1u)) {
+        const uint32_t q = atomicAdd(&s.cnt[dig[r]], 1u);
+        s.keys[q] = keys[r];
+        if (W) s.wts[q] = wts[r];
+      }
+    __syncthreads();
+    for (uint32_t idx = tid; idx < (uint32_t)m; idx += STREAM_NT) {
+      const K key = s.keys[idx];
+      const uint64_t o = s.gbase[msd_digit(key, bits, level)] + idx;
+      dst[o] = key;
+      if (W) dstw[o] = s.wts[idx];
+    }
+    __syncthreads();
+    return;
   }
-  __syncthreads();
+  // two halves: keys r < 8 of every thread, then r >= 8; a digit's keys of the
+  // first half precede its keys of the second in the destination
+  const uint64_t c0 = H > 1 ? s.cnt0[tid] : c;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const uint64_t ch = h == 0 ? c0 : c - c0;
+    uint64_t mh;
+    const uint64_t exh = block_exclusive_scan<STREAM_NT>(ch, s.wsum, &mh);
+    s.gbase[tid] = base + (h == 0 ? 0 : c0) - exh;
+    s.cnt[tid] = (uint32_t)exh;
+    __syncthreads();
+#pragma unroll
+    for (int r = h * (STREAM_KPT / 2); r < (h + 1) * (STREAM_KPT / 2); ++r)
+      if (r < n && ((valid >> r) & 1u)) {
+        const uint32_t q = atomicAdd(&s.cnt[dig[r]], 1u);
+        s.keys[q] = keys[r];
+        if (W) s.wts[q] = wts[r];
+      }
+    __syncthreads();
+    for (uint32_t idx = tid; idx < (uint32_t)mh; idx += STREAM_NT) {
+      const K key = s.keys[idx];
+      const uint64_t o = s.gbase[msd_digit(key, bits, level)] + idx;
+      dst[o] = key;
+      if (W) dstw[o] = s.wts[idx];
+    }
+    __syncthreads();
+  }
 }
 
 // Second enumeration pass: keys go to cursor0[set][d] plus the number of keys
@@ -713,7 +752,10 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
                                                             const Ctl *ctl) {
   // the staged words share LDS with the partition's key buffer: partition_tile
   // passes a barrier before it writes keys, after every thread has enumerated
-  __shared__ PartLds<K> s;
+  // 128-bit keys: two halves (the enumeration is ALU-heavy and gains from the
+  // extra workgroups; the level scatters keep whole tiles, whose longer runs
+  // write faster)
+  __shared__ PartLds<K, false, sizeof(K) == 16 ? 2 : 1> s;
   if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t nt = ctl->n_tiles;
   const uint64_t t = xcd_tile(blockIdx.x, nt);
@@ -737,7 +779,8 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
     for (int r = 0; r < STREAM_KPT; ++r)
       if (r < n && in_slice(a, keys[r])) valid |= 1u << r;
   }
-  partition_tile<K>(keys, nowt, n, a.bits, 0, nullptr, base, dst, nullptr, s, valid);
+  partition_tile<K, false, sizeof(K) == 16 ? 2 : 1>(keys, nowt, n, a.bits, 0, nullptr, base, dst,
+                                                    nullptr, s, valid);
 }
 
 // ---------------------------------------------------------------------------
