@@ -752,10 +752,10 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
                                                             const Ctl *ctl) {
   // the staged words share LDS with the partition's key buffer: partition_tile
   // passes a barrier before it writes keys, after every thread has enumerated
-  // 128-bit keys: two halves (the enumeration is ALU-heavy and gains from the
-  // extra workgroups; the level scatters keep whole tiles, whose longer runs
-  // write faster)
-  __shared__ PartLds<K, false, sizeof(K) == 16 ? 2 : 1> s;
+  // the tile passes through LDS in two halves: the enumeration is ALU-heavy and
+  // gains from the extra workgroups (the level scatters keep whole tiles, whose
+  // longer runs write faster)
+  __shared__ PartLds<K, false, 2> s;
   if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t nt = ctl->n_tiles;
   const uint64_t t = xcd_tile(blockIdx.x, nt);
@@ -779,7 +779,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
     for (int r = 0; r < STREAM_KPT; ++r)
       if (r < n && in_slice(a, keys[r])) valid |= 1u << r;
   }
-  partition_tile<K, false, sizeof(K) == 16 ? 2 : 1>(keys, nowt, n, a.bits, 0, nullptr, base, dst,
+  partition_tile<K, false, 2>(keys, nowt, n, a.bits, 0, nullptr, base, dst,
                                                     nullptr, s, valid);
 }
 
