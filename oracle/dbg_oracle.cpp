@@ -13,11 +13,10 @@
 //   * nodes: every canonical k-mer (Sec. 2: the lexicographically smaller of a
 //     k-mer and its reverse complement) with the number of read positions whose
 //     k-mer canonicalises to it;
-//   * edges: for every (k+1)-mer z of a read, the canonical bi-directed edge that
-//     STEP-1 of algorithm BiConstruct (Sec. 3) assigns to (x, y) = (z[1..k],
-//     z[2..k+1]), plus one tie-break for the case x^ = y^ (the 8-branch table is
-//     followed branch by branch, then the tie-break is applied); duplicates are
-//     removed and counted (STEP-2).
+//   * edges: for every (k+1)-mer z of a read, the bi-directed edge of Sec. 2
+//     between the k-molecules of (x, y) = (z[1..k], z[2..k+1]), in the canonical
+//     form STEP-1 of algorithm BiConstruct (Sec. 3) gives it (with one reading for
+//     the case x^ = y^); duplicates are removed and counted (STEP-2).
 //   * edges are reported in ascending order of their canonical (k+1)-mer, nodes
 //     in ascending k-mer order (the paper fixes no output order).
 //
@@ -33,8 +32,10 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <string_view>
 #include <thread>
 #include <tuple>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -72,43 +73,30 @@ struct Edge {
   }
 };
 
-// STEP-1 of BiConstruct (Sec. 3): the canonical bi-directed edge of a (k+1)-mer z,
-// written as the paper's table: four cases on which of x, y are canonical, each
-// split on whether x^ <= y^.
+int flip(int o) { return o == PLUS ? MINUS : PLUS; }
+
+// The canonical bi-directed edge of a (k+1)-mer z.  Sec. 2: the consecutive k-mers
+// x = z[1..k] and y = z[2..k+1] join the k-molecules of x and y, and the arrow head
+// at each end says which strand of its molecule the k-mer is ('+' when it is the
+// canonical k-mer).  The same adjacency read along the other strand is rc(y)
+// followed by rc(x): the molecules swapped and both heads flipped.  STEP-1
+// (Sec. 3) names every edge by one of these two readings: the one whose first
+// molecule is the smaller.  When both molecules are the same it does not decide;
+// the reading taken here keeps the one with the smaller orientation pair
+// ('+' < '-'), so that a (k+1)-mer and its reverse complement get one record.
 Edge step1_edge(const std::string &z, int k) {
   const std::string x = z.substr(0, k);
   const std::string y = z.substr(1, k);
   const std::string cx = canonical(x);
   const std::string cy = canonical(y);
-  const bool x_canon = (x == cx);
-  const bool y_canon = (y == cy);
-  Edge e;
-  if (x_canon && y_canon) {
-    if (cx <= cy) e = {cx, cy, PLUS, PLUS};
-    else          e = {cy, cx, MINUS, MINUS};
-  } else if (!x_canon && y_canon) {
-    if (cx <= cy) e = {cx, cy, MINUS, PLUS};
-    else          e = {cy, cx, MINUS, PLUS};
-  } else if (x_canon && !y_canon) {
-    if (cx <= cy) e = {cx, cy, PLUS, MINUS};
-    else          e = {cy, cx, PLUS, MINUS};
-  } else {
-    if (cx <= cy) e = {cx, cy, MINUS, MINUS};
-    else          e = {cy, cx, PLUS, PLUS};
-  }
-  // Tie-break (a reading; the table is silent on it): when both k-mers are the
-  // same k-molecule, (u, v, o1, o2) and its reversal (v, u, not o2, not o1) name
-  // one edge; keep the one with the smaller orientation pair.  Only homopolymer
-  // (k+1)-mers change: without this, z = T^(k+1) and its reverse complement
-  // A^(k+1) would give two different records for one edge.
-  if (cx == cy) {
-    const int r1 = 1 - e.o2, r2 = 1 - e.o1;
-    if (std::make_pair(r1, r2) < std::make_pair(e.o1, e.o2)) {
-      e.o1 = r1;
-      e.o2 = r2;
-    }
-  }
-  return e;
+  const int sx = (x == cx) ? PLUS : MINUS;
+  const int sy = (y == cy) ? PLUS : MINUS;
+  const Edge along = {cx, cy, sx, sy};
+  const Edge against = {cy, cx, flip(sy), flip(sx)};
+  if (cx < cy) return along;
+  if (cy < cx) return against;
+  const bool along_first = std::make_pair(along.o1, along.o2) <= std::make_pair(against.o1, against.o2);
+  return along_first ? along : against;
 }
 
 // The string an edge record spells: sigma(u, o1) followed by the last base of
@@ -260,25 +248,54 @@ void oracle_edge_str(void *h, uint64_t i, char *ubuf, char *vbuf, char *zbuf) {
 void oracle_free(void *h) { delete static_cast<Result *>(h); }
 
 // Probe counts over all reads without building the whole graph: for each of the
-// n_np node probes (canonical k-mers, k bytes each, concatenated) the number of
-// read positions whose k-mer canonicalises to it, and for each of the n_ep edge
-// probes (u, v as k bytes each, orient byte) the number of (k+1)-mers whose STEP-1
-// edge is that record.  Used for sampled checks at sizes the full oracle cannot
-// hold in memory.
+// n_np node probes (k bytes each, concatenated) the number of read positions
+// whose k-mer canonicalises to it, and for each of the n_ep edge probes (u, v as
+// k bytes each, orient byte) the number of (k+1)-mers whose STEP-1 edge is that
+// record.  Used for sampled checks at sizes the full oracle cannot hold in memory.
+//
+// Only a few windows can count toward a probe, and they are found by exact
+// string match before anything is canonicalised.  The canonical k-mer of a window
+// w is w or rc(w) (Sec. 2), so it equals p only if w is p or rc(p).  The edge of a
+// (k+1)-mer w, read back through its spelling (edge_spelling), spells w along one
+// of its two strands: the record (x^, y^, s_x, s_y) spells x followed by the last
+// base of y, which is w, and the swapped record (y^, x^, not s_y, not s_x)
+// spells rc(y) followed by the last base of rc(x), which is rc(w).  So a window
+// can have record e only if it is spell(e) or rc(spell(e)).  Every window equal to
+// one of those two strings is then canonicalised, or given its STEP-1 edge, and
+// compared with the probe exactly as the full build would count it.
 void oracle_probe(const char *bases, const uint64_t *offsets, uint64_t n_reads, int k,
                   int n_threads, const char *node_probes, uint64_t n_np, uint64_t *node_counts,
                   const char *edge_u, const char *edge_v, const uint8_t *edge_orient,
                   uint64_t n_ep, uint64_t *edge_counts) {
-  std::map<std::string, uint64_t> node_index;
-  for (uint64_t i = 0; i < n_np; ++i)
-    node_index[std::string(node_probes + i * k, node_probes + (i + 1) * k)] = i;
-  std::map<Edge, uint64_t> edge_index;
-  for (uint64_t i = 0; i < n_ep; ++i) {
-    Edge e{std::string(edge_u + i * k, edge_u + (i + 1) * k),
-           std::string(edge_v + i * k, edge_v + (i + 1) * k), edge_orient[i] >> 1,
-           edge_orient[i] & 1};
-    edge_index[e] = i;
+  std::vector<std::string> node_key(n_np);
+  std::vector<Edge> edge_key(n_ep);
+  // both strands of every probe's spelling -> the probes that spelling can match
+  std::vector<std::string> spellings;
+  spellings.reserve(2 * (n_np + n_ep));
+  for (uint64_t i = 0; i < n_np; ++i) {
+    node_key[i] = std::string(node_probes + i * k, node_probes + (i + 1) * k);
+    spellings.push_back(node_key[i]);
+    spellings.push_back(reverse_complement(node_key[i]));
   }
+  for (uint64_t i = 0; i < n_ep; ++i) {
+    edge_key[i] = Edge{std::string(edge_u + i * k, edge_u + (i + 1) * k),
+                       std::string(edge_v + i * k, edge_v + (i + 1) * k), edge_orient[i] >> 1,
+                       edge_orient[i] & 1};
+    const std::string s = edge_spelling(edge_key[i]);
+    spellings.push_back(s);
+    spellings.push_back(reverse_complement(s));
+  }
+  std::unordered_map<std::string_view, std::vector<uint64_t>> node_match, edge_match;
+  for (uint64_t i = 0; i < n_np; ++i)
+    for (int r = 0; r < 2; ++r) {
+      auto &probes = node_match[spellings[2 * i + r]];
+      if (probes.empty() || probes.back() != i) probes.push_back(i);
+    }
+  for (uint64_t i = 0; i < n_ep; ++i)
+    for (int r = 0; r < 2; ++r) {
+      auto &probes = edge_match[spellings[2 * (n_np + i) + r]];
+      if (probes.empty() || probes.back() != i) probes.push_back(i);
+    }
   const int T = std::max(1, std::min<int>(resolve_threads(n_threads),
                                           static_cast<int>(std::max<uint64_t>(n_reads, 1))));
   std::vector<std::vector<uint64_t>> nc(T, std::vector<uint64_t>(n_np, 0));
@@ -286,15 +303,23 @@ void oracle_probe(const char *bases, const uint64_t *offsets, uint64_t n_reads, 
   auto work = [&](int t) {
     const uint64_t r0 = n_reads * t / T, r1 = n_reads * (t + 1) / T;
     for (uint64_t i = r0; i < r1; ++i) {
-      const std::string read(bases + offsets[i], bases + offsets[i + 1]);
+      const std::string_view read(bases + offsets[i], offsets[i + 1] - offsets[i]);
       const uint64_t len = read.size();
       for (uint64_t j = 0; j + k <= len; ++j) {
-        auto it = node_index.find(canonical(read.substr(j, k)));
-        if (it != node_index.end()) nc[t][it->second] += 1;
+        auto it = node_match.find(read.substr(j, k));
+        if (it == node_match.end()) continue;
+        const std::string c = canonical(std::string(read.substr(j, k)));
+        for (uint64_t p : it->second)
+          if (c == node_key[p]) nc[t][p] += 1;
       }
       for (uint64_t j = 0; j + k + 1 <= len; ++j) {
-        auto it = edge_index.find(step1_edge(read.substr(j, k + 1), k));
-        if (it != edge_index.end()) ec[t][it->second] += 1;
+        auto it = edge_match.find(read.substr(j, k + 1));
+        if (it == edge_match.end()) continue;
+        const Edge e = step1_edge(std::string(read.substr(j, k + 1)), k);
+        for (uint64_t p : it->second) {
+          const Edge &q = edge_key[p];
+          if (e.u == q.u && e.v == q.v && e.o1 == q.o1 && e.o2 == q.o2) ec[t][p] += 1;
+        }
       }
     }
   };
