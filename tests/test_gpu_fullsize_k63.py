@@ -1,51 +1,41 @@
 """Full-size checks of the 40,000,000-read k = 63 build (3.52 G k-mer positions,
 128-bit keys, more than 2^31 keys per table), built as bench.py builds it: output
-capacity 0.55 x k-mer positions, no edge keys.  The oracle cannot build a graph
-this size in a test's time, so every row is checked for properties that hold at
-any size (order, totals, counts >= 1) on the device, and sampled rows for
-canonical form, endpoint membership and the record <-> (k+1)-mer round trip."""
+capacity 0.55 x k-mer positions, no edge keys.
+
+The oracle cannot build a graph this size, so the build is checked three ways:
+  * every row, on the device, against properties that hold at any size: totals,
+    strict order and canonical form of the nodes, strict order of the edges by
+    the (k+1)-mer each spells with every record equal to the STEP-1 record of
+    that (k+1)-mer (Sec. 3), and the degree identity of every node (twice its
+    count = the multiplicities of its edge ends + the reads that begin and end
+    with it), gathered in hashed buckets;
+  * the oracle's probe scan over all 40 M reads for keys sampled from the reads
+    themselves (present nodes and edges, and random keys that must be absent),
+    run on host threads while the GPU builds;
+  * the same scan for rows sampled uniformly from the GPU's tables.
+Every check prints what it is doing before it touches the GPU."""
 
 import gc
 import os
+import threading
+import time
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_1003_1940_amd import synth
+from . import brute
+from . import device_checks as D
 from . import keys_np as K
 from .gpu_util import say
 
 pytestmark = pytest.mark.gpu
 
 k = 63
-CHUNK = 1 << 27  # rows per device-side check, to bound temporaries
-
-
-def _unsigned(t):
-    """int64 bit patterns reordered so that signed order is unsigned order."""
-    import torch
-    return t ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=t.device)
-
-
-def _ascending128(lo, hi):
-    """Strict ascending order of (hi, lo) 128-bit keys held as int64 pairs
-    (columns of one tensor), checked in chunks."""
-    n = lo.numel()
-    for a in range(0, max(n - 1, 0), CHUNK):
-        b = min(n, a + CHUNK + 1)
-        ulo, uhi = _unsigned(lo[a:b]), _unsigned(hi[a:b])
-        ok = (uhi[1:] > uhi[:-1]) | ((uhi[1:] == uhi[:-1]) & (ulo[1:] > ulo[:-1]))
-        if not bool(ok.all()):
-            return False
-    return True
-
-
-def _chunked_sum(t):
-    import torch
-    s = 0
-    for a in range(0, t.numel(), CHUNK):
-        s += int((t[a:a + CHUNK].to(torch.int64) & 0xFFFFFFFF).sum().item())
-    return s
+CHUNK = 1 << 26  # rows per device-side step, to bound temporaries
+N_PROBES = 300
+DEV = "cuda"
 
 
 def _find128(klo, khi, qlo, qhi):
@@ -53,20 +43,68 @@ def _find128(klo, khi, qlo, qhi):
     vectorised binary search on the device that gathers only the probed rows."""
     import torch
     n = klo.numel()
-    qul, quh = _unsigned(qlo), _unsigned(qhi)
     lo = torch.zeros_like(qlo)
     hi = torch.full_like(qlo, n)
     while bool((lo < hi).any()):
         mid = (lo + hi) // 2
         midc = mid.clamp(max=n - 1)
-        mh, ml = _unsigned(khi[midc]), _unsigned(klo[midc])
-        below = (mh < quh) | ((mh == quh) & (ml < qul))
+        below = D.less(klo[midc], khi[midc], qlo, qhi)
         active = lo < hi
         lo = torch.where(active & below, mid + 1, lo)
         hi = torch.where(active & ~below, mid, hi)
     idx = lo.clamp(max=n - 1)
-    hit = (lo < n) & (_unsigned(khi[idx]) == quh) & (_unsigned(klo[idx]) == qul)
+    hit = (lo < n) & (klo[idx] == qlo) & (khi[idx] == qhi)
     return torch.where(hit, lo, torch.full_like(lo, -1))
+
+
+def _orient(o1, o2):
+    return (int(o1 == "-") << 1) | int(o2 == "-")
+
+
+def _record(s):
+    """The STEP-1 record of a (k+1)-mer string, from the Sec. 2 definition
+    (tests/brute.py), with the orientation as (o1 << 1) | o2."""
+    x, y = s[:k], s[1:]
+    u, v, o1, o2 = brute.representative((brute.molecule(x), brute.molecule(y),
+                                         brute.strand(x), brute.strand(y)))
+    return u, v, _orient(o1, o2)
+
+
+def _read_probes(rs, rng):
+    """Nodes and edges at random read positions (present), and random keys
+    (almost surely absent: the probe scan decides)."""
+    nodes, edges = [], []
+    off = rs.offsets
+    for r in rng.integers(0, rs.n_reads, N_PROBES):
+        a, b = int(off[r]), int(off[r + 1])
+        j = int(rng.integers(0, b - a - k))
+        s = bytes(rs.bases[a + j:a + j + k + 1]).decode()
+        nodes.append(brute.molecule(s[:k]))
+        edges.append(_record(s))
+    for _ in range(N_PROBES // 3):
+        s = "".join("ACGT"[c] for c in rng.integers(0, 4, k + 1))
+        nodes.append(brute.molecule(s[:k]))
+        edges.append(_record(s))
+    return nodes, edges
+
+
+class _Probe(threading.Thread):
+    """The oracle's probe scan over all reads on host threads (the ctypes call
+    releases the interpreter lock, so the GPU work goes on meanwhile)."""
+
+    def __init__(self, rs, nodes, edges):
+        super().__init__(daemon=True)
+        self.rs, self.nodes, self.edges = rs, nodes, edges
+        self.result = self.error = None
+
+    def run(self):
+        try:
+            t0 = time.perf_counter()
+            self.result = oracle.probe_counts(self.rs.bases, self.rs.offsets, k, self.nodes,
+                                              self.edges)
+            self.seconds = time.perf_counter() - t0
+        except Exception as e:  # reported by the test that joins
+            self.error = e
 
 
 @pytest.fixture(scope="module")
@@ -75,66 +113,227 @@ def large_full():
     if not torch.cuda.is_available():
         pytest.fail("no GPU visible: the GPU tests need the MI355X")
     from paper_1003_1940_amd import api
+    oracle.build(force=False)
     say("[gpu-fullsize-k63] generating 40,000,000 reads (forked workers draw them)")
     rs = synth.plain_large(workers=max(1, min(16, os.cpu_count() or 1)))
     n_k, n_e = rs.kmer_count(k), rs.kmer_count(k + 1)
+    probe_nodes, probe_edges = _read_probes(rs, np.random.default_rng(6301))
+    scan = _Probe(rs, probe_nodes, probe_edges)
+    say(f"[gpu-fullsize-k63] oracle probe scan of {len(probe_nodes)} nodes and "
+        f"{len(probe_edges)} edges over all reads, on host threads")
+    scan.start()
     cap = int(n_k * 0.55)
     say(f"[gpu-fullsize-k63] building: {n_k} k-mers, output capacity {cap}")
-    g = api.build(rs.bases, rs.offsets, k, zkey=False, node_cap=cap, edge_cap=cap)
-    del rs
+    packed, offs, n_bases = api.upload(rs.bases, rs.offsets)
+    out = api.alloc_outputs(k, cap, cap, zkey=False)
+    ws = api.Workspace(rs.n_reads, 1, n_k, k)
+    result = torch.zeros(3, dtype=torch.int64, device=DEV)
+    api.build_async(packed, n_bases, offs, k, n_k, out, cap, cap, result, ws)
+    n_nodes, n_edges, status = api.read_result(result)
+    del ws, packed, offs
     gc.collect()
-    yield g, n_k, n_e
-    del g
+    torch.cuda.empty_cache()
+    g = api.Graph(k, out["node_kmer"], out["node_count"], out["edge_u"], out["edge_v"],
+                  out["edge_orient"], out["edge_mult"], None, n_nodes, n_edges, status)
+    say(f"[gpu-fullsize-k63] status {status}, {n_nodes} nodes, {n_edges} edges")
+    st = dict(rs=rs, g=g, n_k=n_k, n_e=n_e, scan=scan, probe_nodes=probe_nodes,
+              probe_edges=probe_edges, z=None)
+    yield st
+    scan.join()
+    st.clear()
+    del g, out
     gc.collect()
     torch.cuda.empty_cache()  # later tests size their budgets from free HBM
 
 
+def _z_column(st):
+    """The canonical (k+1)-mer each edge row spells, computed on the device for
+    every row (kept for the lookups of the probe tests)."""
+    import torch
+    if st["z"] is None:
+        g = st["g"]
+        n = g.n_edges
+        zlo = torch.empty(n, dtype=torch.int64, device=DEV)
+        zhi = torch.empty_like(zlo)
+        for a in range(0, n, CHUNK):
+            b = min(n, a + CHUNK)
+            u, v = g.edge_u[a:b], g.edge_v[a:b]
+            o = g.edge_orient[a:b].to(torch.int64)
+            lo, hi = D.spell(u[:, 0], u[:, 1], v[:, 0], v[:, 1], o >> 1, o & 1, k)
+            zlo[a:b], zhi[a:b], _ = D.canonical(lo, hi, k + 1)
+        st["z"] = (zlo, zhi)
+    return st["z"]
+
+
 def test_k63_fullsize_status_and_totals(large_full):
-    g, n_k, n_e = large_full
+    g = large_full["g"]
     assert g.status == 0, f"device status {g.status}"
     assert 0 < g.n_nodes <= g.node_count.numel() and 0 < g.n_edges <= g.edge_mult.numel()
-    say(f"[gpu-fullsize-k63] {g.n_nodes} nodes, {g.n_edges} edges")
     cnt, mult = g.node_count[:g.n_nodes], g.edge_mult[:g.n_edges]
-    assert _chunked_sum(cnt) == n_k, "node counts do not add up to the k-mer positions"
-    assert _chunked_sum(mult) == n_e, "edge multiplicities do not add up to the (k+1)-mers"
+    total_c = sum(int(D.u32(cnt[a:a + CHUNK]).sum()) for a in range(0, g.n_nodes, CHUNK))
+    total_m = sum(int(D.u32(mult[a:a + CHUNK]).sum()) for a in range(0, g.n_edges, CHUNK))
+    assert total_c == large_full["n_k"], "node counts do not add up to the k-mer positions"
+    assert total_m == large_full["n_e"], "edge multiplicities do not add up to the (k+1)-mers"
     assert not bool((cnt == 0).any()) and not bool((mult == 0).any())
 
 
-def test_k63_fullsize_node_order(large_full):
-    g, _, _ = large_full
-    keys = g.node_kmer[:g.n_nodes]
-    assert _ascending128(keys[:, 0], keys[:, 1]), "node keys are not strictly ascending"
+def test_k63_fullsize_nodes_ascending_and_canonical(large_full):
+    g = large_full["g"]
+    say(f"[gpu-fullsize-k63] node order and canonical form over {g.n_nodes} rows")
+    keys = g.node_kmer
+    n = g.n_nodes
+    for a in range(0, n, CHUNK):
+        b = min(n, a + CHUNK + 1)
+        lo, hi = keys[a:b, 0], keys[a:b, 1]
+        assert bool(D.less(lo[:-1], hi[:-1], lo[1:], hi[1:]).all()), \
+            f"node keys not strictly ascending in rows {a}..{b}"
+        rlo, rhi = D.revcomp(lo, hi, k)
+        assert bool(D.less(lo, hi, rlo, rhi).all()), \
+            f"a node key in rows {a}..{b} is not the smaller strand (odd k)"
 
 
-def test_k63_fullsize_sampled_rows(large_full):
+def test_k63_fullsize_edges_ascending_and_records(large_full):
+    """Every edge row: the canonical (k+1)-mer it spells ascends strictly over
+    the whole table, and the STEP-1 record of that (k+1)-mer is the row."""
     import torch
-    g, _, _ = large_full
-    rng = np.random.default_rng(63)
-    ni = torch.from_numpy(np.sort(rng.choice(g.n_nodes, 2000, replace=False))).cuda()
+    g = large_full["g"]
+    say(f"[gpu-fullsize-k63] edge order and record round trip over {g.n_edges} rows")
+    zlo, zhi = _z_column(large_full)
+    n = g.n_edges
+    for a in range(0, n, CHUNK):
+        b = min(n, a + CHUNK)
+        e = min(n, b + 1)
+        assert bool(D.less(zlo[a:e - 1], zhi[a:e - 1], zlo[a + 1:e], zhi[a + 1:e]).all()), \
+            f"edges not in strictly ascending (k+1)-mer order in rows {a}..{e}"
+        ulo, uhi, vlo, vhi, o1, o2 = D.record_of(zlo[a:b], zhi[a:b], k)
+        o = g.edge_orient[a:b].to(torch.int64)
+        same = ((ulo == g.edge_u[a:b, 0]) & (uhi == g.edge_u[a:b, 1]) &
+                (vlo == g.edge_v[a:b, 0]) & (vhi == g.edge_v[a:b, 1]) &
+                (o1 == (o >> 1)) & (o2 == (o & 1)))
+        assert bool(same.all()), f"an edge row in {a}..{b} is not the record of its (k+1)-mer"
+
+
+def test_k63_fullsize_degree_identity(large_full):
+    """For every node v: 2 count(v) = sum over its edge ends of the edge's
+    multiplicity (a self-loop has two ends) + reads whose first k-mer is v +
+    reads whose last k-mer is v.  Each term is added to a bucket chosen by a
+    hash of v (and, weighted by a second hash, to another set of buckets); every
+    bucket must come out zero."""
+    import torch
+    g, rs = large_full["g"], large_full["rs"]
+    say("[gpu-fullsize-k63] degree identity over every node, edge end and read end")
+    acc = D.BucketSums(DEV, bits=26)
+    n, m = g.n_nodes, g.n_edges
+    for a in range(0, n, CHUNK):
+        b = min(n, a + CHUNK)
+        acc.add(g.node_kmer[a:b, 0], g.node_kmer[a:b, 1], 2 * D.u32(g.node_count[a:b]))
+    for a in range(0, m, CHUNK):
+        b = min(m, a + CHUNK)
+        neg = -D.u32(g.edge_mult[a:b])
+        acc.add(g.edge_u[a:b, 0], g.edge_u[a:b, 1], neg)
+        acc.add(g.edge_v[a:b, 0], g.edge_v[a:b, 1], neg)
+    off = rs.offsets.astype(np.int64)
+    lens = np.diff(off)
+    step = 1 << 22
+    for r0 in range(0, rs.n_reads, step):
+        r1 = min(rs.n_reads, r0 + step)
+        sel = np.nonzero(lens[r0:r1] >= k)[0] + r0
+        if len(sel) == 0:
+            continue
+        base = int(off[r0])
+        chunk = torch.from_numpy(rs.bases[base:int(off[r1])].copy()).to(DEV)
+        codes = D.codes_of(chunk)
+        for starts in (off[sel] - base, off[sel + 1] - k - base):
+            lo, hi = D.window_keys(codes, torch.from_numpy(starts).to(DEV), k)
+            clo, chi, _ = D.canonical(lo, hi, k)
+            acc.add(clo, chi, torch.full_like(clo, -1))
+    bad = acc.nonzero()
+    assert bad == 0, f"the degree identity fails in {bad} hashed buckets"
+
+
+def _lookup_nodes(g, strings):
+    import torch
+    keys = [K.from_str(s) for s in strings]
+    qlo = torch.tensor([np.int64(np.uint64(a)) for a, _ in keys], device=DEV)
+    qhi = torch.tensor([np.int64(np.uint64(b)) for _, b in keys], device=DEV)
+    idx = _find128(g.node_kmer[:g.n_nodes, 0], g.node_kmer[:g.n_nodes, 1], qlo, qhi)
+    cnt = D.u32(g.node_count[idx.clamp(min=0)])
+    return torch.where(idx >= 0, cnt, torch.zeros_like(cnt)).cpu().numpy()
+
+
+def _lookup_edges(st, records):
+    """GPU multiplicity of each record (u, v, orient), found through the
+    canonical (k+1)-mer it spells; 0 when the table has no such row, and the row
+    found must hold exactly that record."""
+    import torch
+    g = st["g"]
+    zlo, zhi = _z_column(st)
+    q = []
+    for u, v, o in records:
+        s = brute.spell((u, v, "+-"[o >> 1], "+-"[o & 1]))
+        q.append(K.from_str(brute.molecule(s)))
+    qlo = torch.tensor([np.int64(np.uint64(a)) for a, _ in q], device=DEV)
+    qhi = torch.tensor([np.int64(np.uint64(b)) for _, b in q], device=DEV)
+    idx = _find128(zlo, zhi, qlo, qhi)
+    found = (idx >= 0).cpu().numpy()
+    rows = idx.clamp(min=0)
+    u = g.edge_u[rows].cpu().numpy().view(np.uint64)
+    v = g.edge_v[rows].cpu().numpy().view(np.uint64)
+    o = g.edge_orient[rows].cpu().numpy()
+    mult = D.u32(g.edge_mult[rows]).cpu().numpy()
+    out = np.zeros(len(records), np.uint64)
+    for i, (ru, rv, ro) in enumerate(records):
+        if not found[i]:
+            continue
+        assert (K.to_str(u[i, 0], u[i, 1], k), K.to_str(v[i, 0], v[i, 1], k), int(o[i])) == \
+            (ru, rv, ro), f"the row spelling edge {i}'s (k+1)-mer holds another record"
+        out[i] = mult[i]
+    return out
+
+
+def test_k63_fullsize_probe_counts_from_reads(large_full):
+    """Keys drawn from the reads (and random absent keys), counted by the oracle
+    over all 40 M reads while the GPU built the tables."""
+    st = large_full
+    say("[gpu-fullsize-k63] waiting for the oracle probe scan")
+    st["scan"].join()
+    scan = st["scan"]
+    if scan.error is not None:
+        raise scan.error
+    say(f"[gpu-fullsize-k63] probe scan took {scan.seconds:.1f} s on "
+        f"{oracle.host_threads(0)} host threads")
+    nc, ec = scan.result
+    assert (nc[:N_PROBES] > 0).all() and (ec[:N_PROBES] > 0).all(), \
+        "a key taken from a read has no occurrence in the oracle's scan"
+    got_n = _lookup_nodes(st["g"], st["probe_nodes"])
+    assert np.array_equal(got_n, nc), \
+        f"node counts differ at probes {np.nonzero(got_n != nc)[0][:10]}"
+    got_e = _lookup_edges(st, st["probe_edges"])
+    assert np.array_equal(got_e, ec), \
+        f"edge multiplicities differ at probes {np.nonzero(got_e != ec)[0][:10]}"
+
+
+def test_k63_fullsize_probe_counts_of_rows(large_full):
+    """Rows drawn uniformly from the GPU's tables (mostly keys seen once),
+    counted by the oracle over all reads."""
+    st = large_full
+    g, rs = st["g"], st["rs"]
+    rng = np.random.default_rng(6302)
+    import torch
+    ni = torch.from_numpy(np.sort(rng.choice(g.n_nodes, N_PROBES, replace=False))).to(DEV)
+    ei = torch.from_numpy(np.sort(rng.choice(g.n_edges, N_PROBES, replace=False))).to(DEV)
     nk = g.node_kmer[ni].cpu().numpy().view(np.uint64)
-    lo, hi = nk[:, 0].copy(), nk[:, 1].copy()
-    rlo, rhi = K.revcomp(lo, hi, k)
-    assert K.less(lo, hi, rlo, rhi).all(), "a node key is not strictly canonical (odd k)"
-    # consecutive sampled edges: records round-trip through their (k+1)-mer and
-    # come in ascending order of it
-    start = int(rng.integers(0, g.n_edges - 2001))
-    sl = slice(start, start + 2000)
-    u = g.edge_u[sl].cpu().numpy().view(np.uint64)
-    v = g.edge_v[sl].cpu().numpy().view(np.uint64)
-    o = g.edge_orient[sl].cpu().numpy()
-    o1, o2 = (o >> 1) & 1, o & 1
-    zlo, zhi, _ = K.spell(u[:, 0].copy(), u[:, 1].copy(), v[:, 0].copy(), v[:, 1].copy(), o1, o2, k)
-    zlo, zhi, _ = K.canonical(zlo, zhi, k + 1)
-    assert K.less(zlo[:-1], zhi[:-1], zlo[1:], zhi[1:]).all(), "edges not in (k+1)-mer order"
-    rec = K.record_of(zlo, zhi, k)
-    assert np.array_equal(rec[0], u[:, 0]) and np.array_equal(rec[1], u[:, 1])
-    assert np.array_equal(rec[2], v[:, 0]) and np.array_equal(rec[3], v[:, 1])
-    assert np.array_equal(rec[4], o1) and np.array_equal(rec[5], o2)
-    assert not K.less(v[:, 0], v[:, 1], u[:, 0], u[:, 1]).any(), "an edge has u > v"
-    # both endpoints of sampled edges are nodes
-    keys = g.node_kmer[:g.n_nodes]
-    ei = torch.from_numpy(rng.choice(g.n_edges, 2000, replace=False)).cuda()
-    for col in (g.edge_u, g.edge_v):
-        q = col[ei]
-        found = _find128(keys[:, 0], keys[:, 1], q[:, 0].contiguous(), q[:, 1].contiguous())
-        assert bool((found >= 0).all()), "an edge endpoint is not a node"
+    cnt = D.u32(g.node_count[ni]).cpu().numpy()
+    u = g.edge_u[ei].cpu().numpy().view(np.uint64)
+    v = g.edge_v[ei].cpu().numpy().view(np.uint64)
+    o = g.edge_orient[ei].cpu().numpy()
+    mult = D.u32(g.edge_mult[ei]).cpu().numpy()
+    nodes = [K.to_str(a, b, k) for a, b in nk]
+    edges = [(K.to_str(u[i, 0], u[i, 1], k), K.to_str(v[i, 0], v[i, 1], k), int(o[i]))
+             for i in range(N_PROBES)]
+    say("[gpu-fullsize-k63] oracle probe scan of sampled output rows over all reads")
+    t0 = time.perf_counter()
+    nc, ec = oracle.probe_counts(rs.bases, rs.offsets, k, nodes, edges)
+    say(f"[gpu-fullsize-k63] probe scan took {time.perf_counter() - t0:.1f} s")
+    assert np.array_equal(nc, cnt), f"node counts differ at rows {ni.cpu().numpy()[nc != cnt][:10]}"
+    assert np.array_equal(ec, mult), f"edge counts differ at rows {ei.cpu().numpy()[ec != mult][:10]}"

@@ -211,3 +211,25 @@ def test_pack_rejects_non_acgt():
     a = torch.tensor(list(b"ACGTNACGT"), dtype=torch.uint8, device="cuda")
     _, res = api.pack(a)
     assert api.read_result(res)[2] == 8
+
+
+@pytest.mark.parametrize("k,read_len,n_reads", [(31, 100, 20000), (63, 150, 12000)])
+def test_shared_prefix_deep_levels(k, read_len, n_reads):
+    """Reads that all begin with one 20-base head.  The k-mers that start inside
+    the head share up to 40 leading bits, so thousands of distinct keys stay in
+    one bucket through the first partition levels and split only at level 4 or 5
+    into many LDS batches: the deep levels run on buckets of distinct keys, not
+    only on repeats of one key.  A quarter of the reads repeat earlier ones and
+    30% are reverse-complemented (their last k-mers canonicalise into the same
+    buckets), so the buckets also hold duplicates of both strands."""
+    rng = np.random.default_rng(2000 + k)
+    head = np.concatenate([[0, 1], rng.integers(0, 4, 18)])  # "AC..." keeps it canonical
+    n_unique = n_reads * 3 // 4
+    codes = rng.integers(0, 4, size=(n_unique, read_len)).astype(np.uint8)
+    codes[:, :20] = head
+    codes = np.concatenate([codes, codes[rng.integers(0, n_unique, n_reads - n_unique)]])
+    flip = rng.random(n_reads) < 0.3
+    codes[flip] = 3 - codes[flip, ::-1]
+    bases = np.frombuffer(b"ACGT", np.uint8)[codes].reshape(-1).copy()
+    offsets = np.arange(n_reads + 1, dtype=np.uint64) * np.uint64(read_len)
+    compare_with_oracle(bases, offsets, k, label=f"shared 20-base head, {n_reads} reads")
