@@ -175,6 +175,7 @@ int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
  *   base+2 after the enumeration  base+7 after run counting
  *          histogram (one kernel) base+8 after the run-length write (one kernel)
  *   base+3 after bucket planning  base+9 table end
+ *          (and the node table's records from edge endpoints, when taken)
  *   base+4 after the enumeration scatter (one kernel)
  * n_events must be >= DBG_STAGE_EVENTS.  Process-wide setting, meant for
  * single-stream benchmarking; pass NULL to stop recording. */
@@ -208,9 +209,9 @@ typedef struct {
   float endpoint_ratio; /* for DBG_NODES_AUTO; default 0.6 */
   /* Shape of the LDS bucket sort: 0 = 512-thread workgroups holding up to 6,144
    * keys (64-bit; 3,072 for 128-bit keys), one per CU; 1 = 256-thread
-   * workgroups holding half as many, two per CU; 2 = for 64-bit keys
-   * 768-thread workgroups holding 6,144 keys (three waves per SIMD instead of
-   * two), for 128-bit keys the same as 0.  Default 2. */
+   * workgroups holding half as many, two per CU; 2 = the batch of 0 with more
+   * threads: 768 for 64-bit keys (three waves per SIMD instead of two), 1,024
+   * for 128-bit keys (four instead of two).  Default 2. */
   int local_variant;
   /* Added to the width of the first partition of each batch's distinct keys
    * (normally log2 of their number, 8 to 11 bits), in [-3, 3].  Default 0. */

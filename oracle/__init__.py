@@ -21,21 +21,29 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dbg_oracle.cpp")
-_LIB = os.path.join(_HERE, "libdbg_oracle.so")
+# DBG_ORACLE_LIB names another build of the same source to load instead (the
+# sanitizer build, in the test that runs the pins under it)
+_LIB = os.environ.get("DBG_ORACLE_LIB") or os.path.join(_HERE, "libdbg_oracle.so")
+_LIB_ASAN = os.path.join(_HERE, "libdbg_oracle_asan.so")
 _lib = None
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle into ``oracle/libdbg_oracle.so`` (g++ -O2, C++17)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle into ``oracle/libdbg_oracle.so`` (g++ -O2, C++17), or
+    with ``sanitize`` into ``oracle/libdbg_oracle_asan.so`` with AddressSanitizer
+    and UndefinedBehaviorSanitizer (any report aborts)."""
+    out = _LIB_ASAN if sanitize else _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        extra = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"] if sanitize else ["-O2"])
+        subprocess.run(["g++", *extra, "-std=c++17", "-fPIC", "-shared", "-pthread",
                         "-Wall", "-Wextra", "-o", tmp, _SRC], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 def _load(path: str | None = None):

@@ -117,7 +117,7 @@ def load():
 
 def get_tuning() -> dict:
     """The process-wide build tuning: node_path (NODES_AUTO, NODES_KMERS or
-    NODES_ENDPOINTS), endpoint_ratio, local_variant (0 or 1) and lds_digit_bias."""
+    NODES_ENDPOINTS), endpoint_ratio, local_variant (0, 1 or 2) and lds_digit_bias."""
     t = _Tuning()
     rc = load().dbg_get_tuning(ctypes.byref(t))
     if rc:
@@ -349,8 +349,7 @@ def build(bases: np.ndarray, offsets: np.ndarray, k: int, zkey: bool = True, dev
     sliced to its true sizes.  ``max_keys`` (at least the number of k-mer
     positions, the default) sizes the workspace."""
     offsets = np.asarray(offsets, np.uint64)
-    lens = np.diff(offsets.astype(np.int64))
-    n_k = int(np.maximum(lens - k + 1, 0).sum()) if len(lens) else 0
+    n_k, _ = bounds(offsets, k)
     max_keys = n_k if max_keys is None else max(int(max_keys), n_k)
     packed, offs, n_bases = upload(bases, offsets, device)
     node_cap = n_k if node_cap is None else node_cap
@@ -375,8 +374,7 @@ def build_batched(bases: np.ndarray, offsets: np.ndarray, set_read_offsets: np.n
     per set with row offsets in node_set_offsets / edge_set_offsets."""
     offsets = np.asarray(offsets, np.uint64)
     sro = np.asarray(set_read_offsets, np.uint64)
-    lens = np.diff(offsets.astype(np.int64))
-    n_k = int(np.maximum(lens - k + 1, 0).sum()) if len(lens) else 0
+    n_k, _ = bounds(offsets, k)
     packed, offs, n_bases = upload(bases, offsets, device)
     out = alloc_outputs(k, n_k, n_k, device, zkey)
     n_sets = len(sro) - 1

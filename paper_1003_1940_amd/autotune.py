@@ -3,8 +3,8 @@
 Every knob of ``dbg_tuning_t`` leaves the tables unchanged and moves only the
 time: the node-table route (k-mers or edge endpoints), the workgroup shape of the
 LDS bucket sort (512 threads with the largest batch; 256 threads with half the
-batch and two workgroups per CU; or, for 64-bit keys, 768 threads with the
-largest batch) and the bias of the first partition's digit
+batch and two workgroups per CU; or the largest batch with 768 threads for
+64-bit keys, 1,024 for 128-bit keys) and the bias of the first partition's digit
 width inside a batch.  ``tune`` builds one input under every candidate setting,
 checks that all of them produce bit-identical tables, times each, and returns
 the fastest.  ``TuneCache`` keeps the choices in a JSON file keyed by an input
@@ -83,8 +83,7 @@ def tune(bases: np.ndarray, offsets: np.ndarray, k: int, settings: list | None =
     import torch
     settings = candidates() if settings is None else settings
     offsets = np.asarray(offsets, np.uint64)
-    lens = np.diff(offsets.astype(np.int64))
-    n_k = int(np.maximum(lens - k + 1, 0).sum()) if len(lens) else 0
+    n_k, _ = api.bounds(offsets, k)
     packed, offs, n_bases = api.upload(bases, offsets, device)
     out = api.alloc_outputs(k, n_k, n_k, device, zkey=True)
     ws = api.Workspace(len(offsets) - 1, 1, n_k, k, device)

@@ -51,6 +51,7 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
   // (at most one partial tile per bucket more)
   const uint64_t rows = L.max_tiles + L.item_cap;
   L.thist = take((rows + 1) * 256 * sizeof(uint32_t));
+  L.titem = take(rows * sizeof(uint32_t));
   L.csum = take(((rows + 63) / 64 + 1) * 256 * sizeof(uint32_t));
   L.cursor0 = take(n_sets * 256 * sizeof(uint64_t));
   for (int i = 0; i < 2; ++i) L.items[i] = take(L.item_cap * sizeof(Item));
@@ -60,8 +61,11 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
   L.uniform = take(L.item_cap * sizeof(Item));
   L.rle_heads = take(L.rle_tiles * sizeof(uint64_t));
   L.bits = take(L.rle_tiles * (TILE / 8));
+  // the count of each distinct key, at the key's position in buffer 0
+  L.counts = take((max_keys + 2) * sizeof(uint32_t));
   L.set_uoff = 0;
-  // key buffers: after the bucket sort buffer 0 holds distinct keys, buffer 1 their counts
+  // key buffers: ping-pong for the partition levels; after the bucket sort
+  // buffer 0 holds the distinct keys
   const size_t kb = (max_keys + 2) * (size_t)L.key_bytes;
   for (int i = 0; i < 2; ++i) L.keys[i] = take(kb);
   // weighted records: keys in [0, R w), weights from here on (R <= this / w)

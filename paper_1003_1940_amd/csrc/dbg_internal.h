@@ -24,10 +24,12 @@ constexpr uint64_t TILE = (uint64_t)STREAM_NT * STREAM_KPT;
 // the 64-bit variant holds fewer keys.  V selects the workgroup shape: 0 = 512
 // threads and the largest batch that fits the 160 KB of LDS (one workgroup per
 // CU), 1 = 256 threads and half the batch (two workgroups per CU: more batches
-// in flight for small inputs, more keys left for deeper partition levels).
+// in flight for small inputs, more keys left for deeper partition levels),
+// 2 = the batch of 0 with more threads (768 for 64-bit keys, 1024 for 128-bit
+// keys): the same LDS, more waves to hide its latency.
 template <typename K, bool W = false, int V = 0> struct LocalCfg {
   static_assert(V >= 0 && V <= 2, "three workgroup shapes");
-  static constexpr int NT = V == 1 ? 256 : (V == 2 && sizeof(K) == 8) ? 768 : 512;
+  static constexpr int NT = V == 1 ? 256 : V == 2 ? (sizeof(K) == 8 ? 768 : 1024) : 512;
   static constexpr int CAP = (sizeof(K) == 8 ? (W ? 5120 : 6144) : 3072) >> (V == 1 ? 1 : 0);
   static constexpr int SLOTS = CAP * 3 / 2;
   static constexpr int SMALL = sizeof(K) == 8 ? 16 : 8;  // segments sorted by one lane's network
@@ -78,6 +80,8 @@ struct Batch {  // consecutive small buckets [off, off + size) of buffer `src`
 struct Layout {
   size_t ctl, set_read_off, rbase, block_sums, set_kbase, set_tbase, tile_read, tile_set;
   size_t thist, csum, cursor0, items[2], hist[2], cursor, batches, uniform, rle_heads, bits, set_uoff;
+  size_t counts;  // uint32 count of each distinct key, beside buffer 0
+  size_t titem;   // uint32 item of every tile of a partition level
   size_t keys[2];
   size_t weights;  // byte offset of the record weights inside each key buffer
   size_t total;

@@ -687,15 +687,16 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
     }
   __syncthreads();
   const uint64_t c = s.cnt[tid];
-  uint64_t m;
-  const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &m);
-  // destination of the first key of digit tid
+  // destination of the first key of digit tid, reserved before the scan and the
+  // placement below and only read after them: at deep levels the cursors are
+  // spread over many buckets and the atomic's round trip goes to memory
   const uint64_t base =
       cursor ? (c ? (uint64_t)atomicAdd((unsigned long long *)&cursor[tid], (unsigned long long)c)
                   : 0)
              : my_base;
+  uint64_t m;
+  const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &m);
   if (H == 1) {
-    s.gbase[tid] = base - ex;
     s.cnt[tid] = (uint32_t)ex;
     __syncthreads();
 #pragma unroll
@@ -705,6 +706,7 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
         s.keys[q] = keys[r];
         if (W) s.wts[q] = wts[r];
       }
+    s.gbase[tid] = base - ex;
     __syncthreads();
     for (uint32_t idx = tid; idx < (uint32_t)m; idx += STREAM_NT) {
       const K key = s.keys[idx];
@@ -942,6 +944,26 @@ __global__ __launch_bounds__(1024) void k_level_prep(Item *items, const uint64_t
   }
 }
 
+// Every tile of a level's list to the item it belongs to (one workgroup per item
+// at a time, its threads over the item's tiles), so that the level kernels find a
+// tile's bucket with one load.
+__global__ __launch_bounds__(256) void k_level_tilemap(const Item *items,
+                                                       const uint64_t *n_items_p,
+                                                       const uint64_t *n_tiles_p, uint32_t *titem,
+                                                       uint64_t titem_cap, Ctl *ctl, int gate) {
+  if (ctl->status || gated_off(ctl, gate)) return;
+  const uint64_t n_items = *n_items_p, n_tiles = *n_tiles_p;
+  if (n_tiles > titem_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_status(ctl, DBG_E_INTERNAL);
+    return;
+  }
+  for (uint64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
+    const uint64_t t0 = items[ii].tbase;
+    const uint64_t t1 = ii + 1 < n_items ? items[ii + 1].tbase : n_tiles;
+    for (uint64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) titem[t] = (uint32_t)ii;
+  }
+}
+
 struct LevelArgs {
   const Item *items;
   const uint64_t *n_items_p;
@@ -950,6 +972,7 @@ struct LevelArgs {
   uint32_t *tpre;     // per-tile digit counts, then their column prefix (tile mode), or null
   uint64_t *cursor;
   uint32_t *w0, *w1;  // record weights beside buffers 0 and 1 (weighted scatter)
+  const uint32_t *titem;  // the item of every tile (k_level_tilemap)
   int bits;
   int level;
   int gate;
@@ -963,16 +986,6 @@ struct LevelArgs {
 __device__ __forceinline__ uint64_t item_end_tile(const Item *items, uint64_t ii, uint64_t n_items,
                                                   uint64_t n_tiles) {
   return ii + 1 < n_items ? items[ii + 1].tbase : n_tiles;
-}
-
-__device__ __forceinline__ uint64_t find_item(const Item *items, uint64_t n, uint64_t t) {
-  uint64_t lo = 0, hi = n;  // last item with tbase <= t
-  while (hi - lo > 1) {
-    const uint64_t mid = (lo + hi) >> 1;
-    if (items[mid].tbase <= t) lo = mid;
-    else hi = mid;
-  }
-  return lo;
 }
 
 template <typename K>
@@ -997,7 +1010,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K 
   if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t n_tiles = *a.n_tiles_p, n_items = *a.n_items_p;
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const uint64_t ii = find_item(a.items, n_items, t);
+    const uint64_t ii = a.titem[t];
     const Item it = a.items[ii];
     const uint64_t start = it.off + (t - it.tbase) * TILE;
     const uint64_t end = it.off + it.size < start + TILE ? it.off + it.size : start + TILE;
@@ -1046,7 +1059,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0,
   const uint64_t x0 = (blockIdx.x % N_XCD) * per;
   const uint64_t x1 = x0 + per < n_tiles ? x0 + per : n_tiles;
   for (uint64_t t = x0 + blockIdx.x / N_XCD; t < x1; t += gridDim.x / N_XCD) {
-    const uint64_t ii = find_item(a.items, n_items, t);
+    const uint64_t ii = a.titem[t];
     const Item it = a.items[ii];
     const uint64_t start = it.off + (t - it.tbase) * TILE;
     const uint64_t end = it.off + it.size < start + TILE ? it.off + it.size : start + TILE;
@@ -1326,11 +1339,11 @@ __device__ __forceinline__ void mark_positions(uint32_t *bits, uint64_t off, uin
 }
 
 // The batch's distinct keys, sorted in buffer 0, replace its first positions in
-// b0, their counts go to the same positions of b1, and the bitmap marks those
-// positions.  Reads LDS only.
+// b0, their counts go to the same positions of the 32-bit count array, and the
+// bitmap marks those positions.  Reads LDS only.
 template <typename S, bool W>
 __device__ __forceinline__ void write_batch(S &s, const Batch &bt, uint32_t nu,
-                                            typename S::Key *b0, typename S::Key *b1,
+                                            typename S::Key *b0, uint32_t *cnts,
                                             uint32_t *bits) {
   using K = typename S::Key;
   using CT = typename S::CT;
@@ -1338,7 +1351,7 @@ __device__ __forceinline__ void write_batch(S &s, const Batch &bt, uint32_t nu,
   const CT *cnt0 = s.c0();
   for (uint32_t u = threadIdx.x; u < nu; u += S::NT) {
     b0[bt.off + u] = key0[u];
-    b1[bt.off + u] = (K)((uint32_t)cnt0[u] >> (W ? 1 : 0));
+    cnts[bt.off + u] = (uint32_t)cnt0[u] >> (W ? 1 : 0);
   }
   mark_positions(bits, bt.off, bt.size, nu);
 }
@@ -1349,8 +1362,8 @@ __device__ __forceinline__ void write_batch(S &s, const Batch &bt, uint32_t nu,
 // below hb into buffer 0, sort every bucket of up to 64 keys by ranking each key
 // against the others, refine the rare larger pieces, then write the sorted
 // distinct keys over the batch's first positions of b0, their counts (halved for
-// weighted records) to the same positions of b1, and mark those positions in the
-// bitmap (write_batch).  Ends with a barrier.  The caller must have passed a
+// weighted records) to the same positions of the count array, and mark those
+// positions in the bitmap (write_batch).  Ends with a barrier.  The caller must have passed a
 // barrier after its last read of the LDS the buffers overwrite.  DEFER: the
 // sorted keys are left in buffer 0 for the caller to write out later (every
 // thread has passed a barrier since they were placed).
@@ -1358,14 +1371,18 @@ template <typename S, bool W, int UPT, bool DEFER = false>
 __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[UPT],
                                              const uint32_t (&uc)[UPT], uint32_t nu, int hb,
                                              int dw_bias, const Batch &bt,
-                                             typename S::Key *b0, typename S::Key *b1,
+                                             typename S::Key *b0, uint32_t *cnts,
                                              uint32_t *bits) {
   using K = typename S::Key;
   using CT = typename S::CT;
   constexpr int NT = S::NT, NW = S::NW;
-  static_assert(NW * 256 == 4 * NT, "the first partition's bins: 4 per thread");
-  static_assert(4 * NT <= S::CAP, "bucket starts are kept in the distinct-key list");
-  constexpr int MAXDW = NW >= 8 ? 11 : 10;  // log2 of the NW * 256 bins
+  constexpr int MAXDW = NW >= 8 ? 11 : 10;  // log2 of the first partition's bins
+  // the first partition's bins, BPT per thread; their starts are kept in the
+  // distinct-key list, so there are at most CAP of them
+  constexpr int BINS = NW * 256 <= S::CAP ? NW * 256 : (1 << MAXDW);
+  constexpr int BPT = BINS / NT;
+  static_assert(BPT * NT == BINS && BINS <= S::CAP && (1 << MAXDW) <= BINS,
+                "first-partition bins: a whole number per thread, at most CAP");
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   K *key0 = s.k0();
   CT *cnt0 = s.c0();
@@ -1387,21 +1404,21 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
   }
   __syncthreads();
   if (tid == 0) s.nuniq = 0;  // every thread holds nu; ready for the next batch
-  // thread t owns bins 4t .. 4t+3
-  uint32_t c4[4], st4[4], sum4 = 0;
+  // thread t owns bins BPT t .. BPT t + BPT - 1
+  uint32_t c4[BPT], st4[BPT], sum4 = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    c4[q] = H[4 * tid + q];
+  for (int q = 0; q < BPT; ++q) {
+    c4[q] = H[BPT * tid + q];
     sum4 += c4[q];
   }
   uint32_t tot;
   uint32_t run = block_exclusive_scan<NT>(sum4, s.wsum, &tot);
   uint16_t *bstart = s.ulist;  // the list is read out: it now keeps the bucket starts
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < BPT; ++q) {
     st4[q] = run;
-    H[4 * tid + q] = run;
-    bstart[4 * tid + q] = (uint16_t)run;
+    H[BPT * tid + q] = run;
+    bstart[BPT * tid + q] = (uint16_t)run;
     run += c4[q];
   }
   __syncthreads();
@@ -1444,7 +1461,7 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
       cnt0[fin[j]] = (CT)uc[j];
     }
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < BPT; ++q)
     if (c4[q] > 64u) classify_segment(s, st4[q], c4[q], dshift, 0u, 0);
   __syncthreads();
   // pieces left over (usually none): refined until every piece is finished
@@ -1518,7 +1535,7 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
     __syncthreads();
   }
   if (!DEFER) {
-    write_batch<S, W>(s, bt, nu, b0, b1, bits);
+    write_batch<S, W>(s, bt, nu, b0, cnts, bits);
     __syncthreads();
   }
 }
@@ -1592,7 +1609,7 @@ __device__ __forceinline__ void record_claims(S &s, uint32_t claimed, uint32_t n
 template <typename K, bool W, int V>
 __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     const Batch *batches, const uint64_t *n_batches_p, K *b0, K *b1, const uint32_t *w0,
-    const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate, int dw_bias) {
+    const uint32_t *w1, uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate, int dw_bias) {
   using S = LocalLds<K, W, V>;
   constexpr int NT = S::NT, NW = S::NW, SLOTS = S::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
@@ -1639,7 +1656,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     // keys would otherwise also wait for these stores) and read out of buffer 0
     // before the keys are staged over it
     if (bi != blockIdx.x) {
-      write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
+      write_batch<S, W>(s, prev, prev_nu, b0, cnts, bits);
       __syncthreads();
     }
     // stage the keys
@@ -1732,18 +1749,18 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
         tcnt[q] = 0;
       }
     }
-    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
+    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, cnts, bits);
     prev = bt;
     prev_nu = nu;
   }
-  if (blockIdx.x < n_batches) write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
+  if (blockIdx.x < n_batches) write_batch<S, W>(s, prev, prev_nu, b0, cnts, bits);
 }
 
 template <bool W, int V>
 __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdgpu_waves_per_eu(LocalCfg<uint64_t, W, V>::WAVES_PER_EU))) void k_local_sort64(
     const Batch *batches, const uint64_t *n_batches_p, uint64_t *b0, uint64_t *b1,
-    const uint32_t *w0, const uint32_t *w1, uint32_t *bits, const Ctl *ctl, int gate,
-    int dw_bias) {
+    const uint32_t *w0, const uint32_t *w1, uint32_t *cnts, uint32_t *bits, const Ctl *ctl,
+    int gate, int dw_bias) {
   using S = SlotLds<W, V>;
   using K = uint64_t;
   constexpr int NT = S::NT, NW = S::NW, SLOTS = S::SLOTS;
@@ -1793,7 +1810,7 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
     }
     // the previous batch's output, issued only now: the wait for this batch's
     // keys (above) would otherwise also wait for these stores
-    if (bi != blockIdx.x) write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
+    if (bi != blockIdx.x) write_batch<S, W>(s, prev, prev_nu, b0, cnts, bits);
     __syncthreads();  // read out before the region is cleared
     if (s.dirty) {  // uniform: set before the previous batch's last barrier
       uint4 *r4 = reinterpret_cast<uint4 *>(s.r);
@@ -1877,18 +1894,18 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
         tcnt[q] = 0;
       }
     }
-    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, b1, bits);
+    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, cnts, bits);
     prev_nu = nu;
     prev = bt;
   }
-  if (blockIdx.x < n_batches) write_batch<S, W>(s, prev, prev_nu, b0, b1, bits);
+  if (blockIdx.x < n_batches) write_batch<S, W>(s, prev, prev_nu, b0, cnts, bits);
 }
 
 // Oversized buckets whose digits are exhausted hold one key repeated: one
 // distinct key whose count is the bucket size.
 template <typename K>
 __global__ void k_uniform_emit(const Item *uni, const uint64_t *n_uni_p, K *b0, K *b1,
-                               uint32_t *bits, const Ctl *ctl, int gate) {
+                               uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate) {
   if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t n = *n_uni_p;
   for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < n;
@@ -1896,7 +1913,7 @@ __global__ void k_uniform_emit(const Item *uni, const uint64_t *n_uni_p, K *b0, 
     const Item it = uni[u];
     const K key = (it.src ? b1 : b0)[it.off];
     b0[it.off] = key;
-    b1[it.off] = (K)it.size;
+    cnts[it.off] = (uint32_t)it.size;
     atomicOr(&bits[it.off >> 5], 1u << (it.off & 31));
   }
 }
@@ -1906,8 +1923,9 @@ __global__ void k_uniform_emit(const Item *uni, const uint64_t *n_uni_p, K *b0, 
 template <typename K>
 __global__ __launch_bounds__(256) void k_uniform_emit_w(const Item *uni, const uint64_t *n_uni_p,
                                                         K *b0, K *b1, const uint32_t *w0,
-                                                        const uint32_t *w1, uint32_t *bits,
-                                                        const Ctl *ctl, int gate) {
+                                                        const uint32_t *w1, uint32_t *cnts,
+                                                        uint32_t *bits, const Ctl *ctl,
+                                                        int gate) {
   __shared__ uint64_t wsum[256 / 64 + 1];
   if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t n = *n_uni_p;
@@ -1921,7 +1939,7 @@ __global__ __launch_bounds__(256) void k_uniform_emit_w(const Item *uni, const u
     if (threadIdx.x == 0) {
       const K key = (it.src ? b1 : b0)[it.off];
       b0[it.off] = key;
-      b1[it.off] = (K)(tot >> 1);
+      cnts[it.off] = (uint32_t)(tot >> 1);
       atomicOr(&bits[it.off >> 5], 1u << (it.off & 31));
     }
     __syncthreads();
@@ -2021,7 +2039,7 @@ __global__ void k_rec_init(Ctl *ctl, Item *items0, uint64_t *hist0) {
 
 // ---------------------------------------------------------------------------
 // 5. Emit the tables.  Every position marked in the bitmap holds a distinct key
-// (buffer 0) and its count (buffer 1), and marked positions are in key order
+// (buffer 0) and its count (the count array), and marked positions are in key order
 // within each read set, so the output row of a marked position is the number of
 // marked positions before it.  Tiles of TILE positions (128 bitmap words, one
 // per thread).
@@ -2057,8 +2075,8 @@ constexpr int EMIT_WNT = 256;
 template <typename K, bool EDGES>
 __global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
                                                          const uint64_t *tile_base, const K *b0,
-                                                         const K *b1, OutArgs o, uint64_t n_tiles,
-                                                         const Ctl *ctl) {
+                                                         const uint32_t *cnts, OutArgs o,
+                                                         uint64_t n_tiles, const Ctl *ctl) {
   __shared__ uint32_t wpre[EMIT_NT + 1];  // marked positions before each word of the tile
   __shared__ uint32_t wbits[EMIT_NT];
   __shared__ uint64_t wsum[EMIT_WNT / 64 + 1];
@@ -2093,7 +2111,7 @@ __global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
     const uint64_t j = base + i;
     if (j >= o.capacity) break;
     const K key = b0[pos];
-    o.count[j] = (uint32_t)b1[pos];
+    o.count[j] = cnts[pos];
     if (EDGES) {
       K u, v;
       uint32_t orient;
@@ -2198,15 +2216,15 @@ static inline void stage(int idx, hipStream_t st) {
 template <typename K, bool W, int V>
 static void launch_local_sort(unsigned grid, hipStream_t st, const Batch *batches,
                               const uint64_t *n_batches, K *x0, K *x1, const uint32_t *wt0,
-                              const uint32_t *wt1, uint32_t *bits, const Ctl *ctl, int gate,
-                              int bias) {
+                              const uint32_t *wt1, uint32_t *cnts, uint32_t *bits,
+                              const Ctl *ctl, int gate, int bias) {
   if constexpr (sizeof(K) == 8)
     hipLaunchKernelGGL((k_local_sort64<W, V>), dim3(grid), dim3(LocalCfg<K, W, V>::NT), 0, st,
                        batches, n_batches, reinterpret_cast<uint64_t *>(x0),
-                       reinterpret_cast<uint64_t *>(x1), wt0, wt1, bits, ctl, gate, bias);
+                       reinterpret_cast<uint64_t *>(x1), wt0, wt1, cnts, bits, ctl, gate, bias);
   else
     hipLaunchKernelGGL((k_local_sort<K, W, V>), dim3(grid), dim3(LocalCfg<K, W, V>::NT), 0, st,
-                       batches, n_batches, x0, x1, wt0, wt1, bits, ctl, gate, bias);
+                       batches, n_batches, x0, x1, wt0, wt1, cnts, bits, ctl, gate, bias);
 }
 
 // A grid rounded up to a multiple of the XCD count.
@@ -2248,6 +2266,9 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   K *x0 = reinterpret_cast<K *>(ws + L.keys[0]);
   K *x1 = reinterpret_cast<K *>(ws + L.keys[1]);
   uint32_t *runbits = reinterpret_cast<uint32_t *>(ws + L.bits);
+  uint32_t *cnts = reinterpret_cast<uint32_t *>(ws + L.counts);
+  uint32_t *titem = reinterpret_cast<uint32_t *>(ws + L.titem);
+  const uint64_t titem_cap = L.max_tiles + L.item_cap;
   uint32_t *wt0 = reinterpret_cast<uint32_t *>(ws + L.keys[0] + L.weights);
   uint32_t *wt1 = reinterpret_cast<uint32_t *>(ws + L.keys[1] + L.weights);
   hipStream_t st = A.stream;
@@ -2294,6 +2315,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   else
     hipLaunchKernelGGL((k_enum_hist<K, false>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0,
                        st, ea, thist, ctl);
+  stage(ev + 2, st);
   if (two_routes) {
     const K *eu = static_cast<const K *>(A.edges.u);
     const uint64_t rec_tiles = (2 * A.edges.capacity + 2 * A.n_reads + TILE - 1) / TILE;
@@ -2301,7 +2323,6 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                        eu, static_cast<const K *>(A.edges.v), A.edges.mult, A.packed, n_words,
                        A.read_offsets, A.k, bits, x0, wt0, thist, ctl);
   }
-  stage(ev + 2, st);
   const unsigned col_chunks = (unsigned)((L.max_tiles + COL_CHUNK - 1) / COL_CHUNK);
   hipLaunchKernelGGL(k_col_reduce, dim3(col_chunks), dim3(256), 0, st, thist, csum,
                      &ctl->n_tiles, ctl, g0);
@@ -2326,17 +2347,19 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   const unsigned level_grid = (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, 8192));
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
   LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], thist, cursor, wt0,
-                wt1, bits, 0, 1};
+                wt1, titem, bits, 0, 1};
+  const unsigned plan_grid = grid_for(L.item_cap, 1, 8192);
   if (two_routes) {
     hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, st, ctl, items[0], hist[0]);
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[0], &ctl->items[0],
                        &ctl->level_tiles[0], &ctl->items[1], ctl, 1);
+    hipLaunchKernelGGL(k_level_tilemap, dim3(plan_grid), dim3(256), 0, st, items[0],
+                       &ctl->items[0], &ctl->level_tiles[0], titem, titem_cap, ctl, 1);
     // (the records' tile rows were written by k_records)
     level_prefix(&ctl->level_tiles[0], 1);
     PlanArgs pw{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
                 uniform, L.item_cap, ctl, cap_w, bits, 1};
-    hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
-                       pw, la0);
+    hipLaunchKernelGGL(k_level_plan, dim3(plan_grid), dim3(STREAM_NT), 0, st, pw, la0);
   }
   stage(ev + 3, st);
   if (sliced)
@@ -2353,21 +2376,21 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     const int li = lev & 1;
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[li], &ctl->items[li],
                        &ctl->level_tiles[li], &ctl->items[li ^ 1], ctl, -1);
+    hipLaunchKernelGGL(k_level_tilemap, dim3(plan_grid), dim3(256), 0, st, items[li],
+                       &ctl->items[li], &ctl->level_tiles[li], titem, titem_cap, ctl, -1);
     // levels >= 1 split many buckets at once (at least one per set and top
     // digit), so their atomics spread over many counters: atomic mode
     LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li], hist[li], nullptr, cursor,
-                 wt0, wt1, bits, lev, -1};
+                 wt0, wt1, titem, bits, lev, -1};
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
     PlanArgs pl{items[li ^ 1], &ctl->items[li ^ 1], hist[li ^ 1], L.item_cap, batches,
                 L.batch_cap, uniform, L.item_cap, ctl, cap_u, bits, g0};
-    hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0, st,
-                       pl, la);
+    hipLaunchKernelGGL(k_level_plan, dim3(plan_grid), dim3(STREAM_NT), 0, st, pl, la);
     if (two_routes) {
       PlanArgs pw = pl;
       pw.local_cap = cap_w;
       pw.gate = 1;
-      hipLaunchKernelGGL(k_level_plan, dim3(grid_for(L.item_cap, 1, 1024)), dim3(STREAM_NT), 0,
-                         st, pw, la);
+      hipLaunchKernelGGL(k_level_plan, dim3(plan_grid), dim3(STREAM_NT), 0, st, pw, la);
     }
     la.gate = g0;
     hipLaunchKernelGGL((k_level_scatter<K, false>), dim3(level_grid), dim3(STREAM_NT), 0, st, la,
@@ -2383,30 +2406,30 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                      st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
   const int bias = A.tuning.lds_digit_bias;
   if (lv == 0) {
-    launch_local_sort<K, false, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, runbits,
-                                   ctl, g0, bias);
+    launch_local_sort<K, false, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, cnts,
+                                   runbits, ctl, g0, bias);
     if (two_routes)
       launch_local_sort<K, true, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
-                                    runbits, ctl, 1, bias);
+                                    cnts, runbits, ctl, 1, bias);
   } else if (lv == 1) {
-    launch_local_sort<K, false, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, runbits,
-                                   ctl, g0, bias);
+    launch_local_sort<K, false, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, cnts,
+                                   runbits, ctl, g0, bias);
     if (two_routes)
       launch_local_sort<K, true, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
-                                    runbits, ctl, 1, bias);
+                                    cnts, runbits, ctl, 1, bias);
   } else {
-    launch_local_sort<K, false, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, runbits,
-                                   ctl, g0, bias);
+    launch_local_sort<K, false, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, cnts,
+                                   runbits, ctl, g0, bias);
     if (two_routes)
       launch_local_sort<K, true, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
-                                    runbits, ctl, 1, bias);
+                                    cnts, runbits, ctl, 1, bias);
   }
   stage(ev + 6, st);
   hipLaunchKernelGGL(k_uniform_emit<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
-                     x1, runbits, ctl, g0);
+                     x1, cnts, runbits, ctl, g0);
   if (two_routes)
     hipLaunchKernelGGL(k_uniform_emit_w<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform,
-                       x0, x1, wt0, wt1, runbits, ctl, 1);
+                       x0, x1, wt0, wt1, cnts, runbits, ctl, 1);
   hipLaunchKernelGGL(k_emit_count, dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st, runbits,
                      rle_heads, ctl);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, rle_heads, L.rle_tiles,
@@ -2425,14 +2448,14 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     oa.capacity = capacity = A.edges.capacity;
     set_rows = A.edge_set_offsets;
     hipLaunchKernelGGL((k_emit_write<K, true>), dim3((unsigned)xcd_grid(L.rle_tiles)),
-                       dim3(EMIT_WNT), 0, st, runbits, rle_heads, x0, x1, oa, L.rle_tiles, ctl);
+                       dim3(EMIT_WNT), 0, st, runbits, rle_heads, x0, cnts, oa, L.rle_tiles, ctl);
   } else {
     oa.kmer = A.nodes.kmer;
     oa.count = A.nodes.count;
     oa.capacity = capacity = A.nodes.capacity;
     set_rows = A.node_set_offsets;
     hipLaunchKernelGGL((k_emit_write<K, false>), dim3((unsigned)xcd_grid(L.rle_tiles)),
-                       dim3(EMIT_WNT), 0, st, runbits, rle_heads, x0, x1, oa, L.rle_tiles, ctl);
+                       dim3(EMIT_WNT), 0, st, runbits, rle_heads, x0, cnts, oa, L.rle_tiles, ctl);
   }
   stage(ev + 8, st);
   hipLaunchKernelGGL(k_set_rows, dim3(grid_for(S + 1, 256, 1u << 30)), dim3(256), 0, st, runbits,

@@ -30,9 +30,12 @@ PREFIX_BINS = 1 << PREFIX_BITS
 
 
 def positions(offsets: np.ndarray, length: int) -> int:
-    """Windows of `length` bases inside the reads."""
-    lens = np.diff(np.asarray(offsets, np.uint64).astype(np.int64))
-    return int(np.maximum(lens - length + 1, 0).sum()) if len(lens) else 0
+    """Windows of `length` bases inside the reads (k-mer positions for
+    length = k, (k+1)-mer positions for k + 1), from dbg_bounds."""
+    off = np.asarray(offsets, np.uint64)
+    if length % 2:
+        return api.bounds(off, length)[0]
+    return api.bounds(off, length - 1)[1]
 
 
 def prefix_counts(packed, n_bases: int, offs, k: int, max_positions: int, stream=None):

@@ -83,7 +83,7 @@ def test_fifo_and_tight_budget_agree(served):
     from paper_1003_1940_amd.serve import Request, Server
     reqs, pool, which, _ = served
     fresh = [Request(r.rid, r.bases, r.offsets, r.k, r.arrival_s) for r in reqs[:16]]
-    fifo = Server(slots=1, keep_results=True, zkey=True)
+    fifo = Server(slots=1, keep_results="host", zkey=True)
     st = fifo.run(fresh)
     assert st["peak_inflight"] == 1
     for a, b in zip(fresh, reqs[:16]):
@@ -94,17 +94,86 @@ def test_fifo_and_tight_budget_agree(served):
     need = max(request_bytes(int(r.bases.numel()), int(r.offsets.numel()) - 1,
                              pool[w].kmer_count(r.k), r.k, True)
                for r, w in zip(tight, which[:16]))
-    srv = Server(slots=6, hbm_budget=need, keep_results=True, zkey=True)
+    # results go to host memory, so each build's device memory is given back
+    srv = Server(slots=6, hbm_budget=need, keep_results="host", zkey=True)
     srv.run(tight)
     for a, b in zip(tight, reqs[:16]):
         assert a.status == 0
         _assert_same(_tables(a.graph), _tables(b.graph), f"tight-budget request {a.rid}")
 
 
-def test_request_over_budget_is_refused(served):
-    from paper_1003_1940_amd.serve import Request, Server
-    reqs, _, _, _ = served
-    r = reqs[0]
-    srv = Server(slots=2, hbm_budget=1024)
-    with pytest.raises(ValueError):
-        srv.run([Request(0, r.bases, r.offsets, r.k, 0.0)])
+def _alone(pool, w, k):
+    return gpu_graph(pool[w].bases, pool[w].offsets, k)[1]
+
+
+def test_request_over_budget_is_rejected_alone(served):
+    """A request larger than the budget is rejected with its own status; the
+    requests around it are served and their tables are unchanged."""
+    from paper_1003_1940_amd.serve import REJECTED, Request, Server, request_bytes
+    reqs, pool, which, _ = served
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i].need_bytes)
+    small = [order[0], order[1]]
+    big = order[-1]
+    budget = max(reqs[i].need_bytes for i in small)
+    assert reqs[big].need_bytes > budget
+    run = [Request(j, reqs[i].bases, reqs[i].offsets, reqs[i].k, 0.0)
+           for j, i in enumerate((small[0], big, small[1]))]
+    say("[gpu-serve] over-budget request between two that fit")
+    st = Server(slots=2, hbm_budget=budget, keep_results="host", zkey=True).run(run)
+    assert run[1].status == REJECTED and st["rejected"] == 1
+    for r, i in ((run[0], small[0]), (run[2], small[1])):
+        assert r.status == 0
+        _assert_same(_tables(r.graph), _alone(pool, int(which[i]), r.k), f"request {i}")
+
+
+def test_allocation_failure_fails_only_that_request(served):
+    """With the caching allocator held to a little more than it already holds,
+    a request whose buffers do not fit fails with ALLOC_FAILED (its slot and
+    budget are given back) and the small requests after it are served."""
+    import torch
+    from paper_1003_1940_amd.serve import ALLOC_FAILED, Request, Server, pin_read_set
+    reqs, pool, which, _ = served
+    rng = np.random.default_rng(77)
+    genome = synth.random_genome(rng, 2_000_000)
+    big_rs = synth.sample_reads(rng, genome, 200_000, 100, 0.01)  # needs several hundred MB
+    bb, bo = pin_read_set(big_rs.bases, big_rs.offsets)
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i].need_bytes)[:3]
+    run = [Request(0, bb, bo, 31, 0.0)] + [
+        Request(j + 1, reqs[i].bases, reqs[i].offsets, reqs[i].k, 0.0)
+        for j, i in enumerate(order)]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    total = torch.cuda.get_device_properties(0).total_memory
+    limit = torch.cuda.memory_reserved() + (64 << 20)
+    say(f"[gpu-serve] allocator held to {limit} bytes: the large request must fail")
+    torch.cuda.set_per_process_memory_fraction(limit / total)
+    try:
+        st = Server(slots=1, hbm_budget=1 << 40, keep_results="host", zkey=True).run(run)
+    finally:
+        torch.cuda.set_per_process_memory_fraction(1.0)
+    assert run[0].status == ALLOC_FAILED and st["alloc_failed"] == 1, run[0].error
+    for r, i in zip(run[1:], order):
+        assert r.status == 0, f"request {i}: status {r.status} ({r.error})"
+        _assert_same(_tables(r.graph), _alone(pool, int(which[i]), r.k), f"request {i}")
+
+
+def test_cancel_waiting_requests(served):
+    """One build at a time, everything arriving at once: a request cancelled
+    (from the first request's completion) and one past its deadline never run;
+    the others are served."""
+    from paper_1003_1940_amd.serve import CANCELLED, Request, Server
+    reqs, pool, which, _ = served
+    run = [Request(j, r.bases, r.offsets, r.k, 0.0) for j, r in enumerate(reqs[:5])]
+    run[4].deadline_s = 0.0
+
+    def on_retire(req):
+        if req.rid == 0:
+            run[2].cancel()
+
+    say("[gpu-serve] cancellation of waiting requests")
+    st = Server(slots=1, keep_results="host", zkey=True).run(run, on_retire=on_retire)
+    assert run[2].status == CANCELLED and run[4].status == CANCELLED and st["cancelled"] == 2
+    for j in (0, 1, 3):
+        assert run[j].status == 0
+        _assert_same(_tables(run[j].graph), _alone(pool, int(which[j]), run[j].k),
+                     f"request {j}")
