@@ -78,7 +78,8 @@ typedef enum {
   DBG_E_HIP = 7,        /* a HIP launch failed */
   DBG_E_BASE = 8,       /* a byte other than A, C, G, T (either case) */
   DBG_E_ARG = 9,        /* other invalid argument (e.g. n_sets == 0) */
-  DBG_E_INTERNAL = 10   /* internal list capacity exceeded (a bug) */
+  DBG_E_INTERNAL = 10,  /* internal list capacity exceeded (a bug) */
+  DBG_E_SCRATCH = 11    /* dbg_build_noalloc: the build needs more than its static scratch */
 } dbg_status;
 
 /* Node table outputs (device).  kmer: capacity rows of one uint64_t (k <= 31) or
@@ -145,6 +146,26 @@ int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_off
               uint64_t n_reads, int k, uint64_t max_keys, const dbg_nodes_t *nodes,
               const dbg_edges_t *edges, dbg_result_t *result, void *workspace,
               size_t workspace_bytes, hipStream_t stream);
+
+/* No-allocation build, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it).  The
+ * same build as dbg_build, launch for launch, with the workspace taken from a
+ * static device array of DBG_NOALLOC_SCRATCH_BYTES bytes that the library holds
+ * on every device it runs on until the process ends; the caller still passes
+ * the inputs, the output tables and the result record.  A build that needs more
+ * workspace than that (dbg_workspace_bytes(n_reads, 1, max_keys, k) above
+ * DBG_NOALLOC_SCRATCH_BYTES: about 3.3 M k-mer positions for k <= 31 and 1.7 M
+ * for k >= 33) returns DBG_E_SCRATCH and enqueues nothing.  Every call on a
+ * device shares that device's array and leaves its contents behind (each build
+ * initialises what it reads): calls in stream order on one stream are safe,
+ * calls that overlap on one device (other streams, other threads) race and
+ * must not be issued.  The first call on a device looks up the array's address
+ * there (DBG_E_HIP if that fails); nothing is allocated or freed.  Other errors
+ * as dbg_build. */
+#define DBG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int dbg_build_noalloc(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                      uint64_t n_reads, int k, uint64_t max_keys, const dbg_nodes_t *nodes,
+                      const dbg_edges_t *edges, dbg_result_t *result, hipStream_t stream);
 
 /* Build the graphs of n_sets independent read sets in one launch sequence.  Set s
  * is reads [set_read_offsets[s], set_read_offsets[s+1]) of the same stream

@@ -17,10 +17,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdbg.so")
 
-DBG_OK, DBG_E_CAPACITY = 0, 5
+DBG_OK, DBG_E_CAPACITY, DBG_E_SCRATCH = 0, 5, 11
 _STATUS_NAMES = {0: "DBG_OK", 1: "DBG_E_NULL", 2: "DBG_E_K", 3: "DBG_E_OFFSETS",
                  4: "DBG_E_OVERFLOW", 5: "DBG_E_CAPACITY", 6: "DBG_E_WORKSPACE", 7: "DBG_E_HIP",
-                 8: "DBG_E_BASE", 9: "DBG_E_ARG", 10: "DBG_E_INTERNAL"}
+                 8: "DBG_E_BASE", 9: "DBG_E_ARG", 10: "DBG_E_INTERNAL", 11: "DBG_E_SCRATCH"}
+
+# workspace held by the library for dbg_build_noalloc (DBG_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class DbgError(RuntimeError):
@@ -77,6 +80,9 @@ def load():
         lib.dbg_build.restype = i32
         lib.dbg_build.argtypes = [vp, u64, vp, u64, i32, u64, ctypes.POINTER(_Nodes),
                                   ctypes.POINTER(_Edges), vp, vp, sz, vp]
+        lib.dbg_build_noalloc.restype = i32
+        lib.dbg_build_noalloc.argtypes = [vp, u64, vp, u64, i32, u64, ctypes.POINTER(_Nodes),
+                                          ctypes.POINTER(_Edges), vp, vp]
         lib.dbg_build_batched.restype = i32
         lib.dbg_build_batched.argtypes = [vp, u64, vp, u64, vp, u64, i32, u64,
                                           ctypes.POINTER(_Nodes), ctypes.POINTER(_Edges), vp, vp,
@@ -295,6 +301,23 @@ def build_async(packed, n_bases: int, offsets, k: int, max_keys: int, out: dict,
         where = "dbg_build_batched"
     if rc:
         raise DbgError(rc, where)
+
+
+def build_noalloc_async(packed, n_bases: int, offsets, k: int, max_keys: int, out: dict,
+                        node_cap: int, edge_cap: int, result, stream=None):
+    """Enqueue one build through dbg_build_noalloc: no workspace argument, the
+    library's static per-device scratch is used (builds needing more than
+    NOALLOC_SCRATCH_BYTES raise DBG_E_SCRATCH; calls overlapping on one device
+    race).  All tensors must be resident on the device."""
+    _check_dev(packed, "packed", torch.int64)
+    _check_dev(offsets, "offsets", torch.int64)
+    _check_dev(result, "result", torch.int64)
+    nodes, edges = _structs(out, node_cap, edge_cap)
+    rc = load().dbg_build_noalloc(_ptr(packed), n_bases, _ptr(offsets), offsets.numel() - 1, k,
+                                  max_keys, ctypes.byref(nodes), ctypes.byref(edges),
+                                  _ptr(result), _stream(stream))
+    if rc:
+        raise DbgError(rc, "dbg_build_noalloc")
 
 
 def bounds(offsets: np.ndarray, k: int) -> tuple:

@@ -4,7 +4,37 @@
 
 #include "dbg_internal.h"
 
+// Workspace of dbg_build_noalloc: one array on every device the library runs on,
+// held until the process ends.  In host code the name only stands for the
+// symbol; the array's device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[DBG_NOALLOC_SCRATCH_BYTES];
+
 namespace dbg {
+
+// Device address of the scratch array on each device, looked up once per
+// device with that device current.
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+static int scratch_address(hipStream_t stream, void **out) {
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return DBG_E_HIP;
+  int dev = cur;
+  if (stream && hipStreamGetDevice(stream, &dev) != hipSuccess) return DBG_E_HIP;
+  if (dev < 0 || dev >= MAX_DEVICES) return DBG_E_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return DBG_E_HIP;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return DBG_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DBG_OK;
+}
 
 // Process-wide tuning: copied under the lock at the start of each build call.
 static std::mutex g_tuning_mu;
@@ -136,6 +166,21 @@ int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_off
   a.stream = stream;
   a.tuning = dbg::current_tuning();
   return dbg::run(a, workspace_bytes);
+}
+
+int dbg_build_noalloc(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
+                      uint64_t n_reads, int k, uint64_t max_keys, const dbg_nodes_t *nodes,
+                      const dbg_edges_t *edges, dbg_result_t *result, hipStream_t stream) {
+  if (k < 1 || k > 63 || (k & 1) == 0) return DBG_E_K;
+  if (max_keys >= (1ull << 32)) return DBG_E_OVERFLOW;
+  if (n_reads >= DBG_NOALLOC_SCRATCH_BYTES / sizeof(uint64_t)) return DBG_E_SCRATCH;
+  const size_t need = dbg::make_layout(n_reads, 1, max_keys, k, max_keys).total;
+  if (need > DBG_NOALLOC_SCRATCH_BYTES) return DBG_E_SCRATCH;
+  void *ws = nullptr;
+  const int rc = dbg::scratch_address(stream, &ws);
+  if (rc != DBG_OK) return rc;
+  return dbg_build(packed, n_bases, read_offsets, n_reads, k, max_keys, nodes, edges, result, ws,
+                   DBG_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int dbg_build_batched(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_offsets,
@@ -304,6 +349,7 @@ const char *dbg_strerror(int status) {
     case DBG_E_BASE: return "input byte is not one of A, C, G, T";
     case DBG_E_ARG: return "invalid argument";
     case DBG_E_INTERNAL: return "internal list capacity exceeded";
+    case DBG_E_SCRATCH: return "the build needs more workspace than the no-allocation scratch holds";
   }
   return "unknown status";
 }

@@ -27,7 +27,7 @@ def lib():
 def test_header_declares_entry_points():
     assert declared_functions() == ["dbg_adjacency", "dbg_adjacency_workspace_bytes",
                                     "dbg_bounds", "dbg_build", "dbg_build_batched",
-                                    "dbg_build_slice",
+                                    "dbg_build_noalloc", "dbg_build_slice",
                                     "dbg_compact", "dbg_compact_workspace_bytes",
                                     "dbg_get_tuning", "dbg_pack_ascii", "dbg_prefix_counts",
                                     "dbg_prefix_workspace_bytes", "dbg_set_stage_events",
