@@ -44,9 +44,31 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+STAGE_EVENTS = 24  # DBG_STAGE_EVENTS: 12 per table
+
+
 def stage_names():
-    return ["start", "offsets", "enum_hist", "plan", "enum_scatter", "levels", "local_sort",
-            "emit_count", "emit_write", "end"]
+    """The intervals between a table's stage events (see dbg_set_stage_events)."""
+    return ["start", "offsets", "enum_hist", "plan", "enum_scatter", "levels_in_tile",
+            "seg_sort", "levels_rest", "local_sort", "emit_count", "emit_write", "end"]
+
+
+def table_stages(intervals):
+    """Stage times of one table from its event intervals {name: ms}: the
+    partition levels before and after the digit-range bucket sort are one stage
+    ("levels"); the bucket sort is its two launches, the digit ranges of in-tile
+    buckets ("seg_sort") and the other batches ("local_sort_rest"), whose sum is
+    "local_sort"."""
+    out = {}
+    for n in ("offsets", "enum_hist", "plan", "enum_scatter"):
+        out[n] = intervals[n]
+    out["levels"] = intervals["levels_in_tile"] + intervals["levels_rest"]
+    out["seg_sort"] = intervals["seg_sort"]
+    out["local_sort_rest"] = intervals["local_sort"]
+    out["local_sort"] = intervals["seg_sort"] + intervals["local_sort"]
+    for n in ("emit_count", "emit_write", "end"):
+        out[n] = intervals[n]
+    return out
 
 
 def algorithmic_bytes(stage, n_keys, n_unique, n_bases, n_reads, w, row_bytes):
@@ -403,7 +425,7 @@ def plain_measure(workload, scale, steps, warmup, cap_frac, zkey, node_route="au
         raise SystemExit(f"device status {status}: {api.strerror(status)}")
 
     # per-step stage events (HIP events recorded by the library on `stream`)
-    NE = 20
+    NE = STAGE_EVENTS
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE)] for _ in range(steps)]
     for step_ev in ev:  # torch creates the HIP event on first record
         for e in step_ev:
@@ -429,10 +451,14 @@ def plain_measure(workload, scale, steps, warmup, cap_frac, zkey, node_route="au
 
     names = stage_names()
     stages = {}
-    for tbl, base in (("edges", 0), ("nodes", 10)):
-        for i in range(1, 10):
+    half = NE // 2
+    for tbl, base in (("edges", 0), ("nodes", half)):
+        iv = {}
+        for i in range(1, half):
             vals = [ev[s_][base + i - 1].elapsed_time(ev[s_][base + i]) for s_ in range(steps)]
-            stages[f"{tbl}.{names[i]}"] = float(np.mean(vals))
+            iv[names[i]] = float(np.mean(vals))
+        for n_, v in table_stages(iv).items():
+            stages[f"{tbl}.{n_}"] = v
     log("stages (ms): " + ", ".join(f"{k_}={v:.3f}" for k_, v in stages.items()))
 
     # dominant single-kernel stage and its roofline
@@ -756,14 +782,16 @@ def _stage_of(short_name):
 
 def _table_bytes(seq, scale):
     """One table's dispatches (name, KiB): bytes of each single-kernel stage (the
-    launch that did work: a table of the endpoint route also launches the other
-    route's sort, which returns at once), and of the sort + reduce part."""
+    sum over its launches: the bucket sort is launched for the digit ranges of
+    in-tile buckets and for the other batches, and a table of the endpoint route
+    also launches the other route's kernels, which return at once), and of the
+    sort + reduce part."""
     stages, sr, inside = {}, 0.0, False
     for s, v in seq:
         b = v * 1024 * scale
         st = _stage_of(s)
-        if st is not None and b >= stages.get(st, 0.0):
-            stages[st] = b
+        if st is not None:
+            stages[st] = stages.get(st, 0.0) + b
         if inside:
             sr += b
         base = s.split("::")[-1].split("<")[0]
@@ -895,17 +923,19 @@ def summarize_stats(args):
         per = {}
         for bld in builds:
             for tbl in ("edges", "nodes"):
-                best = {}
+                tot = {}
                 for s, d in bld[tbl]:
                     st = _stage_of(s)
-                    if st is not None and d >= best.get(st, 0.0):
-                        best[st] = d
-                for st, d in best.items():
+                    if st is not None:
+                        tot[st] = tot.get(st, 0.0) + d
+                for st, d in tot.items():
                     per.setdefault(f"{tbl}.{st}", []).append(d)
         if per:
             lines += ["", f"Single-kernel stages per table (mean over the {len(builds)} builds; "
-                      "the bench line's live durations of the same stages come from HIP events "
-                      "on the build stream):", "", "| stage | avg us |", "|---|---|"]
+                      "a stage is the sum of its kernel's launches in the table: the bucket sort "
+                      "runs once over the digit ranges of in-tile buckets and once over the other "
+                      "batches; the bench line's live durations of the same stages come from HIP "
+                      "events on the build stream):", "", "| stage | avg us |", "|---|---|"]
             for n, v in sorted(per.items()):
                 lines.append(f"| {n} | {np.mean(v):.1f} |")
     path = os.path.join(ROOT, "profiles", f"{args.workload}_kernel_stats.md")

@@ -190,17 +190,22 @@ int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,
 /* Profiling aid.  When `events` is non-null, every later build records
  * events[i] (hipEvent_t handles created by the caller) on its stream at fixed
  * stage boundaries, DBG_STAGE_EVENTS per build: for the edge table (base 0)
- * and then the node table (base 10),
- *   base+0 table start            base+5 after the remaining partition levels
- *   base+1 after key offsets      base+6 after the LDS bucket sort (one kernel)
- *   base+2 after the enumeration  base+7 after run counting
- *          histogram (one kernel) base+8 after the run-length write (one kernel)
- *   base+3 after bucket planning  base+9 table end
- *          (and the node table's records from edge endpoints, when taken)
- *   base+4 after the enumeration scatter (one kernel)
+ * and then the node table (base DBG_STAGE_EVENTS / 2),
+ *   base+0 table start             base+6  after the digit-range bucket sort
+ *   base+1 after key offsets               of the in-tile level (one kernel)
+ *   base+2 after the enumeration   base+7  after the remaining partition levels
+ *          histogram (one kernel)  base+8  after the LDS bucket sort of the
+ *   base+3 after bucket planning           other batches (one kernel)
+ *          (and the node table's   base+9  after run counting
+ *          records from edge       base+10 after the run-length write (one
+ *          endpoints, when taken)          kernel)
+ *   base+4 after the enumeration   base+11 table end
+ *          scatter (one kernel)
+ *   base+5 after the partition levels up to the in-tile level (equal to
+ *          base+6 when the build has no in-tile level)
  * n_events must be >= DBG_STAGE_EVENTS.  Process-wide setting, meant for
  * single-stream benchmarking; pass NULL to stop recording. */
-#define DBG_STAGE_EVENTS 20
+#define DBG_STAGE_EVENTS 24
 int dbg_set_stage_events(hipEvent_t *events, int n_events);
 
 /* How the node table is built.  STEP-3 of Sec. 3 gives the node set as the
@@ -237,13 +242,21 @@ typedef struct {
   /* Added to the width of the first partition of each batch's distinct keys
    * (normally log2 of their number, 8 to 11 bits), in [-3, 3].  Default 0. */
   int lds_digit_bias;
-  int reserved[4];      /* zero */
+  /* 128-bit keys: 1 = at the first partition level whose buckets average at
+   * most 65,536 keys per read set, buckets of at most 64 tiles of 4,096 keys are
+   * split within each tile (one read and one write of their keys, no histogram
+   * pass and no global cursors) and the bucket sort reads each digit range as
+   * one segment per tile; 0 = every level scatters through global cursors.
+   * Default 1. */
+  int in_tile;
+  int reserved[3];      /* zero */
 } dbg_tuning_t;
 
 /* Process-wide tuning read by every later build call (calls in flight keep the
  * values they started with).  NULL restores the defaults.  Every setting gives
  * the same tables; only the time changes.  Returns DBG_E_ARG for an unknown
- * node_path or local_variant, a ratio outside [0, 2] or a bias outside [-3, 3]. */
+ * node_path or local_variant, a ratio outside [0, 2], a bias outside [-3, 3] or
+ * an in_tile other than 0 or 1. */
 int dbg_set_tuning(const dbg_tuning_t *tuning);
 /* Copies the current tuning into *tuning (DBG_E_NULL if null). */
 int dbg_get_tuning(dbg_tuning_t *tuning);

@@ -46,7 +46,7 @@ class _Edges(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("node_path", ctypes.c_int), ("endpoint_ratio", ctypes.c_float),
                 ("local_variant", ctypes.c_int), ("lds_digit_bias", ctypes.c_int),
-                ("reserved", ctypes.c_int * 4)]
+                ("in_tile", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class _Chains(ctypes.Structure):
@@ -59,7 +59,7 @@ class _Chains(ctypes.Structure):
                 ("kept_orient", ctypes.c_void_p)]
 
 
-TUNING_FIELDS = ("node_path", "endpoint_ratio", "local_variant", "lds_digit_bias")
+TUNING_FIELDS = ("node_path", "endpoint_ratio", "local_variant", "lds_digit_bias", "in_tile")
 
 
 NODES_AUTO, NODES_KMERS, NODES_ENDPOINTS = -1, 0, 1
@@ -123,18 +123,20 @@ def load():
 
 def get_tuning() -> dict:
     """The process-wide build tuning: node_path (NODES_AUTO, NODES_KMERS or
-    NODES_ENDPOINTS), endpoint_ratio, local_variant (0, 1 or 2) and lds_digit_bias."""
+    NODES_ENDPOINTS), endpoint_ratio, local_variant (0, 1 or 2), lds_digit_bias
+    and in_tile (0 or 1)."""
     t = _Tuning()
     rc = load().dbg_get_tuning(ctypes.byref(t))
     if rc:
         raise DbgError(rc, "dbg_get_tuning")
     return {"node_path": t.node_path, "endpoint_ratio": round(float(t.endpoint_ratio), 6),
-            "local_variant": t.local_variant, "lds_digit_bias": t.lds_digit_bias}
+            "local_variant": t.local_variant, "lds_digit_bias": t.lds_digit_bias,
+            "in_tile": t.in_tile}
 
 
 def set_tuning(node_path: int | None = None, endpoint_ratio: float | None = None,
                local_variant: int | None = None, lds_digit_bias: int | None = None,
-               defaults: bool = False) -> dict:
+               in_tile: int | None = None, defaults: bool = False) -> dict:
     """Change the process-wide tuning (unnamed fields keep their values;
     ``defaults=True`` first restores the library defaults).  Returns the new
     tuning.  Every setting gives identical tables."""
@@ -145,12 +147,12 @@ def set_tuning(node_path: int | None = None, endpoint_ratio: float | None = None
             raise DbgError(rc, "dbg_set_tuning")
     cur = get_tuning()
     new = dict(node_path=node_path, endpoint_ratio=endpoint_ratio, local_variant=local_variant,
-               lds_digit_bias=lds_digit_bias)
+               lds_digit_bias=lds_digit_bias, in_tile=in_tile)
     for f in TUNING_FIELDS:
         if new[f] is None:
             new[f] = cur[f]
     t = _Tuning(int(new["node_path"]), float(new["endpoint_ratio"]), int(new["local_variant"]),
-                int(new["lds_digit_bias"]))
+                int(new["lds_digit_bias"]), int(new["in_tile"]))
     rc = lib.dbg_set_tuning(ctypes.byref(t))
     if rc:
         raise DbgError(rc, "dbg_set_tuning")

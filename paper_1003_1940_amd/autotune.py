@@ -1,7 +1,8 @@
 """Autotuner of the build's run-time knobs.
 
 Every knob of ``dbg_tuning_t`` leaves the tables unchanged and moves only the
-time: the node-table route (k-mers or edge endpoints), the workgroup shape of the
+time: the node-table route (k-mers or edge endpoints), the in-tile partition
+level for 128-bit keys (on or off), the workgroup shape of the
 LDS bucket sort (512 threads with the largest batch; 256 threads with half the
 batch and two workgroups per CU; or the largest batch with 768 threads for
 64-bit keys, 1,024 for 128-bit keys) and the bias of the first partition's digit
@@ -25,15 +26,15 @@ import numpy as np
 from . import api
 
 DEFAULT = {"node_path": api.NODES_AUTO, "endpoint_ratio": 0.6, "local_variant": 2,
-           "lds_digit_bias": 0}
+           "lds_digit_bias": 0, "in_tile": 1}
 
 
 def candidates(node_paths=(api.NODES_KMERS, api.NODES_ENDPOINTS), local_variants=(0, 1, 2),
-               biases=(-1, 0, 1)) -> list:
-    """The settings ``tune`` tries by default: every combination of the given
-    values (18 by default)."""
-    return [dict(DEFAULT, node_path=n, local_variant=v, lds_digit_bias=b)
-            for n, v, b in itertools.product(node_paths, local_variants, biases)]
+               biases=(-1, 0, 1), in_tiles=(1,)) -> list:
+    """Every combination of the given values (18 by default; ``tune`` adds
+    in_tile 0 for 128-bit keys, where the in-tile level exists: 36)."""
+    return [dict(DEFAULT, node_path=n, local_variant=v, lds_digit_bias=b, in_tile=t)
+            for n, v, b, t in itertools.product(node_paths, local_variants, biases, in_tiles)]
 
 
 def input_class(n_kmers: int, n_bases: int, k: int, genome_hint: int | None = None) -> str:
@@ -81,7 +82,8 @@ def tune(bases: np.ndarray, offsets: np.ndarray, k: int, settings: list | None =
     tables differ from the first setting's.  The process-wide tuning is restored
     afterwards."""
     import torch
-    settings = candidates() if settings is None else settings
+    if settings is None:
+        settings = candidates(in_tiles=(1, 0) if k > 31 else (1,))
     offsets = np.asarray(offsets, np.uint64)
     n_k, _ = api.bounds(offsets, k)
     packed, offs, n_bases = api.upload(bases, offsets, device)

@@ -38,7 +38,7 @@ static int scratch_address(hipStream_t stream, void **out) {
 
 // Process-wide tuning: copied under the lock at the start of each build call.
 static std::mutex g_tuning_mu;
-static dbg_tuning_t g_tuning = {DBG_NODES_AUTO, 0.6f, 2, 0, {0, 0, 0, 0}};
+static dbg_tuning_t g_tuning = {DBG_NODES_AUTO, 0.6f, 2, 0, 1, {0, 0, 0}};
 
 static dbg_tuning_t current_tuning() {
   std::lock_guard<std::mutex> lock(g_tuning_mu);
@@ -60,6 +60,9 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
   L.item_cap = max_keys / cap + 2;
   // batches per level <= 2 * keys / cap + parents + oversized children
   L.batch_cap = levels * (2 * (max_keys / cap) + 1) + n_sets + 3 * levels * L.item_cap + 64;
+  // digit ranges of in-tile buckets (one level has them): at most two per
+  // capacity's worth of keys plus one per bucket
+  L.seg_cap = 2 * (max_keys / cap) + L.item_cap + 64;
   L.rle_tiles = (max_keys + TILE - 1) / TILE;
   if (L.rle_tiles == 0) L.rle_tiles = 1;
   L.read_blocks = n_reads / ((uint64_t)256 * 16) + 1;
@@ -88,6 +91,8 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
   for (int i = 0; i < 2; ++i) L.hist[i] = take(L.item_cap * 256 * sizeof(uint64_t));
   L.cursor = take(L.item_cap * 256 * sizeof(uint64_t));
   L.batches = take(L.batch_cap * sizeof(Batch));
+  L.segb = take(L.seg_cap * sizeof(SegBatch));
+  L.segt = take(L.seg_cap * SEG_TILES * sizeof(uint32_t));
   L.uniform = take(L.item_cap * sizeof(Item));
   L.rle_heads = take(L.rle_tiles * sizeof(uint64_t));
   L.bits = take(L.rle_tiles * (TILE / 8));
@@ -315,7 +320,7 @@ int dbg_set_stage_events(hipEvent_t *events, int n_events) {
 }
 
 int dbg_set_tuning(const dbg_tuning_t *tuning) {
-  dbg_tuning_t t = {DBG_NODES_AUTO, 0.6f, 2, 0, {0, 0, 0, 0}};
+  dbg_tuning_t t = {DBG_NODES_AUTO, 0.6f, 2, 0, 1, {0, 0, 0}};
   if (tuning) {
     if (tuning->node_path < DBG_NODES_AUTO || tuning->node_path > DBG_NODES_ENDPOINTS)
       return DBG_E_ARG;
@@ -323,6 +328,7 @@ int dbg_set_tuning(const dbg_tuning_t *tuning) {
     if (tuning->local_variant < 0 || tuning->local_variant >= dbg::LOCAL_VARIANTS)
       return DBG_E_ARG;
     if (tuning->lds_digit_bias < -3 || tuning->lds_digit_bias > 3) return DBG_E_ARG;
+    if (tuning->in_tile != 0 && tuning->in_tile != 1) return DBG_E_ARG;
     t = *tuning;
   }
   std::lock_guard<std::mutex> lock(dbg::g_tuning_mu);

@@ -14,6 +14,7 @@ namespace dbg {
 constexpr int STREAM_NT = 256;
 constexpr int STREAM_KPT = 16;
 constexpr uint64_t TILE = (uint64_t)STREAM_NT * STREAM_KPT;
+constexpr int TILES_NT_WIDE = 512;  // threads of the in-tile pass for 128-bit keys
 
 // LDS-resident bucket sort: a workgroup of NT threads sorts a batch of
 // consecutive small buckets of up to CAP keys entirely in LDS (see
@@ -64,12 +65,30 @@ struct Ctl {
   uint32_t capacity_short;  // an output table had more rows than its capacity
   uint32_t node_path;       // 0: node table from k-mers, 1: from edge endpoints
   uint64_t n_records;       // weighted endpoint records (node_path 1)
+  uint64_t n_seg;           // digit ranges of in-tile buckets planned at the current level
 };
 
 struct Item {  // an oversized bucket: keys [off, off + size) of buffer `src`
   uint64_t off, size, tbase;
-  uint32_t src, pad;
+  uint32_t src;
+  uint32_t in_tile;  // 1: split within each of its tiles (at most SEG_TILES of them)
 };
+
+// Buckets of at most SEG_TILES tiles are split tile by tile: every tile is
+// partitioned by the level's digit in place (its keys move to buffer 1 at the
+// tile's own positions, digit-contiguous, and its 256 digit offsets go to a row),
+// so the keys of a range of digits lie in one segment per tile.
+constexpr int SEG_TILES = 64;
+
+struct SegBatch {  // digits [da, db) of an in-tile bucket: one segment per tile
+  uint64_t out;       // where the range's keys start in sorted order (buffer 0)
+  uint32_t size;      // keys in the range
+  uint32_t tiles;     // tiles of the bucket
+  uint64_t item_off;  // first key of the bucket (its first tile)
+  uint64_t pad;
+};
+// Beside every SegBatch, a table of SEG_TILES words: word i = the range's
+// first and end offsets inside tile i (each at most TILE, 16 bits apiece).
 
 struct Batch {  // consecutive small buckets [off, off + size) of buffer `src`
   uint64_t off;
@@ -81,11 +100,13 @@ struct Layout {
   size_t ctl, set_read_off, rbase, block_sums, set_kbase, set_tbase, tile_read, tile_set;
   size_t thist, csum, cursor0, items[2], hist[2], cursor, batches, uniform, rle_heads, bits, set_uoff;
   size_t counts;  // uint32 count of each distinct key, beside buffer 0
+  size_t segb;    // SegBatch list of the in-tile level
+  size_t segt;    // their segment tables, SEG_TILES words each
   size_t titem;   // uint32 item of every tile of a partition level
   size_t keys[2];
   size_t weights;  // byte offset of the record weights inside each key buffer
   size_t total;
-  uint64_t max_tiles, item_cap, batch_cap, rle_tiles, read_blocks;
+  uint64_t max_tiles, item_cap, batch_cap, seg_cap, rle_tiles, read_blocks;
   int key_bytes;
 };
 

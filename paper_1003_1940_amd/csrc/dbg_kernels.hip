@@ -84,6 +84,7 @@ __global__ void k_table_reset(Ctl *ctl) {
     ctl->n_batches = 0;
     ctl->n_uniform = 0;
     ctl->n_unique = 0;
+    ctl->n_seg = 0;
   }
 }
 
@@ -647,7 +648,7 @@ __global__ __launch_bounds__(256) void k_col_apply(uint32_t *thist, const uint32
 // digit-contiguously in LDS, then write each digit run with consecutive threads
 // on consecutive addresses.  `cursor` points at the 256 bucket cursors of the
 // parent.  Every thread of the workgroup must call it.
-template <typename K, bool W = false, int HV = 1>
+template <typename K, bool W = false, int HV = 1, int NT = STREAM_NT>
 struct PartLds {
   // HV = 2: the tile passes through LDS in two halves (half the LDS, so twice
   // the workgroups per CU; the runs of a digit are written in two pieces)
@@ -660,33 +661,41 @@ struct PartLds {
   uint64_t gbase[256];
   uint32_t cnt[256];
   uint32_t cnt0[HALVES > 1 ? 256 : 1];  // keys of each digit in the first half
-  uint64_t wsum[STREAM_NT / 64 + 1];
+  uint64_t wsum[NT / 64 + 1];
 };
 
-template <typename K, bool W = false, int HV = 1>
-__device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
-                                               const uint32_t (&wts)[STREAM_KPT], int n, int bits,
+template <typename K, bool W = false, int HV = 1, int NT = STREAM_NT>
+__device__ __forceinline__ void partition_tile(const K (&keys)[TILE / NT],
+                                               const uint32_t (&wts)[TILE / NT], int n, int bits,
                                                int level, uint64_t *cursor, uint64_t my_base,
-                                               K *dst, uint32_t *dstw, PartLds<K, W, HV> &s,
-                                               uint32_t valid = 0xffffffffu) {
+                                               K *dst, uint32_t *dstw, PartLds<K, W, HV, NT> &s,
+                                               uint32_t valid = 0xffffffffu,
+                                               uint32_t *row = nullptr) {
   // cursor != null: reserve each digit's range with one atomic on cursor[d];
   // otherwise thread d already holds its digit's destination start in my_base.
-  constexpr int H = HV;
+  // row != null: the tile is written in digit order to my_base onwards (the
+  // same for every thread) and each digit's offset inside the tile to row[d].
+  // Threads 0..255 own the digits; NT >= 256.
+  constexpr int H = HV, KPT = (int)(TILE / NT);
+  static_assert(NT >= 256 && (uint64_t)NT * KPT == TILE, "a digit per thread, whole tile");
   const uint32_t tid = threadIdx.x;
-  uint32_t dig[STREAM_KPT];
+  const bool owner = NT == 256 || tid < 256;
+  uint32_t dig[KPT];
 #pragma unroll
-  for (int r = 0; r < STREAM_KPT; ++r) dig[r] = r < n ? msd_digit(keys[r], bits, level) : 0u;
-  s.cnt[tid] = 0;
-  if (H > 1) s.cnt0[tid] = 0;
+  for (int r = 0; r < KPT; ++r) dig[r] = r < n ? msd_digit(keys[r], bits, level) : 0u;
+  if (owner) {
+    s.cnt[tid] = 0;
+    if (H > 1) s.cnt0[tid] = 0;
+  }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < STREAM_KPT; ++r)
+  for (int r = 0; r < KPT; ++r)
     if (r < n && ((valid >> r) & 1u)) {
       atomicAdd(&s.cnt[dig[r]], 1u);
-      if (H > 1 && r < STREAM_KPT / 2) atomicAdd(&s.cnt0[dig[r]], 1u);
+      if (H > 1 && r < KPT / 2) atomicAdd(&s.cnt0[dig[r]], 1u);
     }
   __syncthreads();
-  const uint64_t c = s.cnt[tid];
+  const uint64_t c = owner ? s.cnt[tid] : 0;
   // destination of the first key of digit tid, reserved before the scan and the
   // placement below and only read after them: at deep levels the cursors are
   // spread over many buckets and the atomic's round trip goes to memory
@@ -695,20 +704,23 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
                   : 0)
              : my_base;
   uint64_t m;
-  const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &m);
+  const uint64_t ex = block_exclusive_scan<NT>(c, s.wsum, &m);
   if (H == 1) {
-    s.cnt[tid] = (uint32_t)ex;
+    if (owner) s.cnt[tid] = (uint32_t)ex;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < STREAM_KPT; ++r)
+    for (int r = 0; r < KPT; ++r)
       if (r < n && ((valid >> r) & 1u)) {
         const uint32_t q = atomicAdd(&s.cnt[dig[r]], 1u);
         s.keys[q] = keys[r];
         if (W) s.wts[q] = wts[r];
       }
-    s.gbase[tid] = base - ex;
+    if (owner) {
+      s.gbase[tid] = row ? base : base - ex;
+      if (row) row[tid] = (uint32_t)ex;
+    }
     __syncthreads();
-    for (uint32_t idx = tid; idx < (uint32_t)m; idx += STREAM_NT) {
+    for (uint32_t idx = tid; idx < (uint32_t)m; idx += NT) {
       const K key = s.keys[idx];
       const uint64_t o = s.gbase[msd_digit(key, bits, level)] + idx;
       dst[o] = key;
@@ -719,6 +731,7 @@ __device__ __forceinline__ void partition_tile(const K (&keys)[STREAM_KPT],
   }
   // two halves: keys r < 8 of every thread, then r >= 8; a digit's keys of the
   // first half precede its keys of the second in the destination
+  static_assert(H == 1 || NT == 256, "halves: 256 threads");
   const uint64_t c0 = H > 1 ? s.cnt0[tid] : c;
 #pragma unroll
   for (int h = 0; h < H; ++h) {
@@ -810,7 +823,30 @@ struct PlanArgs {
   uint64_t local_cap;
   int bits;
   int gate;
+  int in_tile_ok;           // children of at most SEG_TILES tiles are split within tiles
+  SegBatch *segb;           // digit ranges of in-tile parents
+  uint32_t *segt;           // their segment tables (SEG_TILES words each)
+  uint64_t seg_cap;
+  uint64_t *kw0, *kw1;      // key buffers 0 and 1 as 64-bit words (gathers)
+  int key_words;            // 64-bit words per key
+  const uint32_t *rows;     // digit offsets of every tile of an in-tile parent
 };
+
+// An in-tile parent: its tiles' rows give each digit's segment in every tile.
+struct SegParent {
+  uint64_t tbase;  // row of the first tile
+  uint32_t tiles;
+  uint32_t size;
+};
+
+// Offset of digit d's segment inside tile i of an in-tile parent (d = 256: the
+// tile's size).
+__device__ __forceinline__ uint32_t seg_row(const PlanArgs &p, const SegParent &sp, uint32_t i,
+                                            uint32_t d) {
+  if (d < 256) return p.rows[(sp.tbase + i) * 256 + d];
+  const uint64_t rest = (uint64_t)sp.size - (uint64_t)i * TILE;
+  return (uint32_t)(rest < TILE ? rest : TILE);
+}
 
 constexpr uint32_t PLAN_LARGE = 0xffffffffu;
 
@@ -820,26 +856,31 @@ struct PlanLds {
   uint64_t base[3];
   alignas(16) uint32_t sz[256];  // keys of each sub-bucket, PLAN_LARGE if oversized
   uint32_t bchild[256];     // first sub-bucket of each batch
+  uint32_t blast[256];      // last sub-bucket of each batch
   uint32_t bsize[256];      // keys of each batch
   uint32_t nb;
 };
 
 // Called by the whole workgroup (256 threads), thread d passing the count c of
 // sub-bucket d of the parent whose keys start at `off`; children live in buffer
-// `src`; `child_level` is the digit level that would split a child.
+// `src`; `child_level` is the digit level that would split a child.  sp: the
+// parent was split within its tiles (its children lie in one segment per tile of
+// buffer 1): small children go into digit ranges (SegBatch), oversized ones are
+// first gathered into buffer 0 at their place in sorted order.
 __device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint32_t src,
-                              int child_level, uint64_t *cursor, PlanLds &s) {
+                              int child_level, uint64_t *cursor, PlanLds &s,
+                              const SegParent *sp = nullptr) {
   const uint32_t d = threadIdx.x;
   uint64_t total;
   const uint64_t ex = block_exclusive_scan<STREAM_NT>(c, s.wsum, &total);
-  cursor[d] = off + ex;
+  if (!sp) cursor[d] = off + ex;
   const bool large = c > p.local_cap;
   s.ex[d] = ex;
   s.sz[d] = large ? PLAN_LARGE : (uint32_t)c;
   __syncthreads();
   if (d == 0) {
     const uint32_t cap = (uint32_t)p.local_cap;
-    uint32_t nb = 0, first = 0, fill = 0;  // fill = 0: no batch open
+    uint32_t nb = 0, first = 0, last = 0, fill = 0;  // fill = 0: no batch open
     const uint4 *z4 = reinterpret_cast<const uint4 *>(s.sz);
     for (uint32_t q4 = 0; q4 < 64; ++q4) {
       const uint4 v = z4[q4];
@@ -851,17 +892,20 @@ __device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint3
         const bool close = fill && (z == PLAN_LARGE || fill + z > cap);
         if (close) {
           s.bchild[nb] = first;
+          s.blast[nb] = last;
           s.bsize[nb] = fill;
           ++nb;
           fill = 0;
         }
         if (z == PLAN_LARGE) continue;
         if (fill == 0) first = 4 * q4 + (uint32_t)i;
+        last = 4 * q4 + (uint32_t)i;
         fill += z;
       }
     }
     if (fill) {
       s.bchild[nb] = first;
+      s.blast[nb] = last;
       s.bsize[nb] = fill;
       ++nb;
     }
@@ -873,7 +917,8 @@ __device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint3
   // (the scan's barriers also publish nb)
   const uint32_t nb = s.nb;
   if (d == 0) {
-    s.base[0] = nb ? atomicAdd((unsigned long long *)&p.ctl->n_batches, (unsigned long long)nb) : 0;
+    uint64_t *nbat = sp ? &p.ctl->n_seg : &p.ctl->n_batches;
+    s.base[0] = nb ? atomicAdd((unsigned long long *)nbat, (unsigned long long)nb) : 0;
     s.base[1] = n_large && digits_left
                     ? atomicAdd((unsigned long long *)p.next_count, n_large) : 0;
     s.base[2] = n_large && !digits_left
@@ -882,14 +927,50 @@ __device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint3
   __syncthreads();
   if (d < nb) {
     const uint64_t bi = s.base[0] + d;
-    if (bi < p.batch_cap) p.batches[bi] = Batch{off + s.ex[s.bchild[d]], s.bsize[d], src};
-    else set_status(p.ctl, DBG_E_INTERNAL);
+    if (!sp) {
+      if (bi < p.batch_cap) p.batches[bi] = Batch{off + s.ex[s.bchild[d]], s.bsize[d], src};
+      else set_status(p.ctl, DBG_E_INTERNAL);
+    } else {
+      if (bi < p.seg_cap)
+        p.segb[bi] = SegBatch{off + s.ex[s.bchild[d]], s.bsize[d], sp->tiles, off, 0};
+      else set_status(p.ctl, DBG_E_INTERNAL);
+    }
+  }
+  if (sp) {
+    // each digit range's segment table: where it starts and ends in every tile
+    const uint32_t T = sp->tiles;
+    for (uint32_t x = d; x < nb * T; x += STREAM_NT) {
+      const uint32_t b = x / T, i = x - b * T;
+      const uint64_t bi = s.base[0] + b;
+      if (bi < p.seg_cap)
+        p.segt[bi * SEG_TILES + i] =
+            seg_row(p, *sp, i, s.bchild[b]) | seg_row(p, *sp, i, s.blast[b] + 1) << 16;
+    }
+  }
+  if (sp && n_large) {
+    // gather each oversized child: its segment of every tile, in tile order,
+    // from buffer 1 into buffer 0 at its place (the children in between are
+    // never written there: digit ranges write their own places)
+    const uint32_t kw = (uint32_t)p.key_words;
+    for (uint32_t q = 0; q < 256; ++q) {
+      if (s.sz[q] != PLAN_LARGE) continue;  // the same for the whole workgroup
+      uint64_t to = (off + s.ex[q]) * kw;
+      for (uint32_t i = 0; i < sp->tiles; ++i) {
+        const uint32_t lo = seg_row(p, *sp, i, q), hi = seg_row(p, *sp, i, q + 1);
+        const uint64_t from = (off + (uint64_t)i * TILE + lo) * kw;
+        const uint32_t nw = (hi - lo) * kw;
+        for (uint32_t x = d; x < nw; x += STREAM_NT) p.kw0[to + x] = p.kw1[from + x];
+        to += nw;
+      }
+    }
+    src = 0;
   }
   if (large) {
     if (digits_left) {
       const uint64_t ii = s.base[1] + lid;
       if (ii < p.item_cap) {
-        p.next_items[ii] = Item{off + ex, c, 0, src, 0};
+        const uint32_t in_tile = p.in_tile_ok && c <= (uint64_t)SEG_TILES * TILE ? 1u : 0u;
+        p.next_items[ii] = Item{off + ex, c, 0, src, in_tile};
         if (p.next_hist)
           for (int j = 0; j < 256; ++j) p.next_hist[ii * 256 + j] = 0;
       } else {
@@ -973,6 +1054,7 @@ struct LevelArgs {
   uint64_t *cursor;
   uint32_t *w0, *w1;  // record weights beside buffers 0 and 1 (weighted scatter)
   const uint32_t *titem;  // the item of every tile (k_level_tilemap)
+  uint32_t *rows;     // digit offsets inside every tile of in-tile items
   int bits;
   int level;
   int gate;
@@ -988,13 +1070,13 @@ __device__ __forceinline__ uint64_t item_end_tile(const Item *items, uint64_t ii
   return ii + 1 < n_items ? items[ii + 1].tbase : n_tiles;
 }
 
-template <typename K>
+template <typename K, int NT = STREAM_NT>
 __device__ __forceinline__ int load_tile(const K *src, uint64_t start, uint64_t end,
-                                         K (&keys)[STREAM_KPT]) {
+                                         K (&keys)[TILE / NT]) {
   int n = 0;
 #pragma unroll
-  for (int r = 0; r < STREAM_KPT; ++r) {
-    const uint64_t i = start + threadIdx.x + (uint64_t)r * STREAM_NT;
+  for (int r = 0; r < (int)(TILE / NT); ++r) {
+    const uint64_t i = start + threadIdx.x + (uint64_t)r * NT;
     if (i < end) {
       keys[r] = src[i];
       n = r + 1;
@@ -1008,14 +1090,32 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K 
                                                           const Ctl *ctl) {
   __shared__ uint32_t h[256];
   if (ctl->status || gated_off(ctl, a.gate)) return;
-  const uint64_t n_tiles = *a.n_tiles_p, n_items = *a.n_items_p;
-  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  const uint64_t n_tiles = *a.n_tiles_p;
+  // a contiguous run of tiles per workgroup: consecutive tiles mostly share their
+  // bucket, whose counts then go out once per run instead of once per tile
+  const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
+  const uint64_t t0 = blockIdx.x * per;
+  const uint64_t t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
+  constexpr uint64_t NONE = ~0ull;
+  uint64_t cur = NONE;
+  Item it{};
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint64_t t = t0; t < t1; ++t) {
     const uint64_t ii = a.titem[t];
-    const Item it = a.items[ii];
+    if (ii != cur) {  // the same for the whole workgroup
+      if (cur != NONE && !a.tpre) {
+        const uint32_t c = h[threadIdx.x];
+        if (c) atomicAdd((unsigned long long *)&a.hist[cur * 256 + threadIdx.x], (unsigned long long)c);
+        h[threadIdx.x] = 0;
+      }
+      __syncthreads();
+      cur = ii;
+      it = a.items[ii];
+    }
+    if (it.in_tile) continue;  // split within its tiles by k_level_tiles
     const uint64_t start = it.off + (t - it.tbase) * TILE;
     const uint64_t end = it.off + it.size < start + TILE ? it.off + it.size : start + TILE;
-    h[threadIdx.x] = 0;
-    __syncthreads();
     K keys[STREAM_KPT];
     // strided layout: key r of thread q is start + q + r * STREAM_NT
     const int n = load_tile<K>(it.src ? b1 : b0, start, end, keys);
@@ -1023,10 +1123,15 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K 
     for (int r = 0; r < STREAM_KPT; ++r)
       if (r < n) atomicAdd(&h[msd_digit(keys[r], a.bits, a.level)], 1u);
     __syncthreads();
+    if (a.tpre) {
+      a.tpre[t * 256 + threadIdx.x] = h[threadIdx.x];
+      h[threadIdx.x] = 0;
+      __syncthreads();
+    }
+  }
+  if (cur != NONE && !a.tpre) {
     const uint32_t c = h[threadIdx.x];
-    if (a.tpre) a.tpre[t * 256 + threadIdx.x] = c;
-    else if (c) atomicAdd((unsigned long long *)&a.hist[ii * 256 + threadIdx.x], (unsigned long long)c);
-    __syncthreads();
+    if (c) atomicAdd((unsigned long long *)&a.hist[cur * 256 + threadIdx.x], (unsigned long long)c);
   }
 }
 
@@ -1036,7 +1141,14 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_plan(PlanArgs p, LevelArgs 
   const uint64_t n_items = *a.n_items_p;
   for (uint64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
     const Item it = a.items[ii];
-    uint64_t c;
+    uint64_t c = 0;
+    if (it.in_tile) {  // the sum over the bucket's tiles of digit d's segment
+      const SegParent sp{it.tbase, (uint32_t)((it.size + TILE - 1) / TILE), (uint32_t)it.size};
+      const uint32_t d = threadIdx.x;
+      for (uint32_t i = 0; i < sp.tiles; ++i) c += seg_row(p, sp, i, d + 1) - seg_row(p, sp, i, d);
+      plan_children(p, c, it.off, 1u, a.level + 1, nullptr, lds, &sp);
+      continue;
+    }
     if (a.tpre) {
       const uint64_t t1 = item_end_tile(a.items, ii, n_items, *a.n_tiles_p);
       c = (uint32_t)(a.tpre[t1 * 256 + threadIdx.x] - a.tpre[it.tbase * 256 + threadIdx.x]);
@@ -1047,10 +1159,16 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_plan(PlanArgs p, LevelArgs 
   }
 }
 
+// Threads of the in-tile pass: its tile of 128-bit keys takes 64 KB of LDS, so
+// two workgroups fit a CU, and 512 threads keep twice the loads in flight (it
+// measured faster than 256; the level scatter measured faster with 256).
+template <typename K> constexpr int tiles_nt() { return sizeof(K) == 16 ? TILES_NT_WIDE : STREAM_NT; }
+
 template <typename K, bool W>
 __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0, K *b1,
                                                              const Ctl *ctl) {
-  __shared__ PartLds<K, W> s;
+  constexpr int NT = STREAM_NT;
+  __shared__ PartLds<K, W, 1, NT> s;
   if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t n_tiles = *a.n_tiles_p, n_items = *a.n_items_p;
   // this XCD's eighth of the tiles, strided over its workgroups (gridDim.x is a
@@ -1061,23 +1179,52 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0,
   for (uint64_t t = x0 + blockIdx.x / N_XCD; t < x1; t += gridDim.x / N_XCD) {
     const uint64_t ii = a.titem[t];
     const Item it = a.items[ii];
+    if (it.in_tile) continue;  // split within its tiles by k_level_tiles
     const uint64_t start = it.off + (t - it.tbase) * TILE;
     const uint64_t end = it.off + it.size < start + TILE ? it.off + it.size : start + TILE;
-    K keys[STREAM_KPT];
+    K keys[TILE / NT];
     // keys are placed through LDS, so any assignment of keys to threads works:
     // use the coalesced strided one (valid keys form a prefix of each thread's)
-    const int n = load_tile<K>(it.src ? b1 : b0, start, end, keys);
-    uint32_t wts[STREAM_KPT] = {};
-    if (W) load_tile<uint32_t>(it.src ? a.w1 : a.w0, start, end, wts);
+    const int n = load_tile<K, NT>(it.src ? b1 : b0, start, end, keys);
+    uint32_t wts[TILE / NT] = {};
+    if (W) load_tile<uint32_t, NT>(it.src ? a.w1 : a.w0, start, end, wts);
     uint64_t *cur = a.cursor + ii * 256;
     uint64_t my_base = 0;
     if (a.tpre) {  // column prefixes are counted modulo 2^32 (a table has < 2^32 keys)
       const uint32_t d = threadIdx.x;
-      my_base = cur[d] + (uint32_t)(a.tpre[t * 256 + d] - a.tpre[it.tbase * 256 + d]);
+      if (d < 256)
+        my_base = cur[d] + (uint32_t)(a.tpre[t * 256 + d] - a.tpre[it.tbase * 256 + d]);
       cur = nullptr;
     }
-    partition_tile<K, W>(keys, wts, n, a.bits, a.level, cur, my_base, it.src ? b0 : b1,
-                         it.src ? a.w0 : a.w1, s);
+    partition_tile<K, W, 1, NT>(keys, wts, n, a.bits, a.level, cur, my_base, it.src ? b0 : b1,
+                                it.src ? a.w0 : a.w1, s);
+  }
+}
+
+// In-tile items: every tile partitioned by the level's digit in LDS and written
+// back whole, digit-contiguous, to buffer 1 at its own positions (in place when
+// the item is already there), with the offset of each digit inside the tile in
+// the tile's row.
+template <typename K>
+__global__ __launch_bounds__(tiles_nt<K>()) void k_level_tiles(LevelArgs a, K *b0, K *b1,
+                                                               const Ctl *ctl) {
+  constexpr int NT = tiles_nt<K>();
+  __shared__ PartLds<K, false, 1, NT> s;
+  if (ctl->status || gated_off(ctl, a.gate)) return;
+  const uint64_t n_tiles = *a.n_tiles_p;
+  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const uint64_t ii = a.titem[t];
+    const Item it = a.items[ii];
+    if (!it.in_tile) continue;
+    const uint64_t start = it.off + (t - it.tbase) * TILE;
+    const uint64_t end = it.off + it.size < start + TILE ? it.off + it.size : start + TILE;
+    K keys[TILE / NT];
+    const int n = load_tile<K, NT>(it.src ? b1 : b0, start, end, keys);
+    const uint32_t nowt[TILE / NT] = {};
+    // every thread has its keys before any key is written (the partition passes
+    // barriers first), so the tile may be rewritten in place
+    partition_tile<K, false, 1, NT>(keys, nowt, n, a.bits, a.level, nullptr, start, b1, nullptr,
+                                    s, 0xffffffffu, a.rows + t * 256);
   }
 }
 
@@ -1557,6 +1704,79 @@ __device__ __forceinline__ Batch desc_unpack(uint32_t v) {
                (uint32_t)__builtin_amdgcn_readlane(v, 3)};
 }
 
+// Digit ranges of in-tile buckets: the descriptor and the segment table read
+// ahead in one VGPR each (descriptor dword l in lane l < 8, table word l in lane
+// l), as desc_lane_load.
+struct SegDesc {
+  uint64_t out, item_off;
+  uint32_t size, tiles;
+};
+// The lane index made opaque where it is used, so that per-lane addresses are
+// formed in the loop rather than kept live across it (they were spilled, and
+// the reloads waited for every memory operation in flight).
+__device__ __forceinline__ uint32_t opaque_lane() {
+  uint32_t l = lane_id();
+  asm volatile("" : "+v"(l));
+  return l;
+}
+__device__ __forceinline__ uint32_t seg_lane_load(const SegBatch *segb, uint64_t i, uint64_t n) {
+  static_assert(sizeof(SegBatch) == 32, "eight dwords");
+  const uint32_t l = opaque_lane();
+  uint32_t v = 0;
+  if (n && l < 8) v = reinterpret_cast<const uint32_t *>(segb + (i < n ? i : n - 1))[l];
+  return v;
+}
+__device__ __forceinline__ uint32_t tab_lane_load(const uint32_t *segt, uint64_t i, uint64_t n) {
+  static_assert(SEG_TILES == 64, "a table word per lane");
+  return n ? segt[(i < n ? i : n - 1) * SEG_TILES + opaque_lane()] : 0u;
+}
+__device__ __forceinline__ SegDesc seg_unpack(uint32_t v) {
+  auto rl = [&](int l) { return (uint32_t)__builtin_amdgcn_readlane(v, l); };
+  return SegDesc{((uint64_t)rl(1) << 32) | rl(0), ((uint64_t)rl(5) << 32) | rl(4), rl(2), rl(3)};
+}
+// Keys of a digit range into registers (key e = tid + j NT as load_batch): the
+// range is the concatenation of its segments in tile order (lane l < tiles holds
+// tile l's segment in `tab`); each wave finds the segment of its 64 keys from the
+// segment starts its lanes hold (ballots, then the few segment boundaries inside
+// the wave's span).  Every lane of the wave must be active.
+template <typename K, int NT, int LPT>
+__device__ __forceinline__ void load_seg(const SegDesc &d, uint32_t tab, const K *b1,
+                                         K (&pre)[LPT]) {
+  const uint32_t l = opaque_lane();
+  const bool mine = l < d.tiles;
+  const uint32_t ra = tab & 0xffffu, rb = tab >> 16;
+  const uint32_t sz = mine ? rb - ra : 0u;
+  const uint32_t S = wave_inclusive_scan(sz) - sz;  // first key of segment l in the range
+  const uint64_t P = d.item_off + (uint64_t)l * TILE + ra;  // its first key in buffer 1
+  // the wave's first key (uniform), then every position before any load is
+  // issued, so that nothing waits between the loads
+  const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u;
+  uint64_t pos[LPT];
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+    const uint32_t e0 = w0 + (uint32_t)j * NT;
+    pos[j] = ~0ull;
+    if (e0 >= d.size) continue;  // the same for the whole wave
+    const uint32_t e = e0 + l;
+    const uint32_t elast = e0 + 63 < d.size ? e0 + 63 : d.size - 1;
+    const int i0 = __popcll(__ballot(mine && S <= e0)) - 1;
+    const int i1 = __popcll(__ballot(mine && S <= elast)) - 1;
+    uint32_t si = (uint32_t)__builtin_amdgcn_readlane(S, i0);
+    uint64_t pi = read_lane(P, i0);
+    for (int q = i0 + 1; q <= i1; ++q) {
+      const uint32_t sq = (uint32_t)__builtin_amdgcn_readlane(S, q);
+      const uint64_t pq = read_lane(P, q);
+      if (e >= sq) {
+        si = sq;
+        pi = pq;
+      }
+    }
+    if (e < d.size) pos[j] = pi + (e - si);
+  }
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) pre[j] = pos[j] != ~0ull ? b1[pos[j]] : K(0);
+}
+
 // Keys (and weights) of a batch into registers: key e = tid + j NT.
 template <typename K, bool W, int NT, int LPT>
 __device__ __forceinline__ void load_batch(const Batch &b, const K *b0, const K *b1,
@@ -1606,10 +1826,15 @@ __device__ __forceinline__ void record_claims(S &s, uint32_t claimed, uint32_t n
 // beside the keys in w0 / w1, are summed per distinct key instead of counting
 // occurrences, and the sum is halved on output (each k-mer occurrence is seen
 // twice).
-template <typename K, bool W, int V>
+// SEG: the batches are the digit ranges of in-tile buckets (segb, one segment
+// per tile in buffer 1, found through the tiles' rows); their sorted distinct
+// keys go to their places in buffer 0 as for any batch.
+template <typename K, bool W, int V, bool SEG = false>
 __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     const Batch *batches, const uint64_t *n_batches_p, K *b0, K *b1, const uint32_t *w0,
-    const uint32_t *w1, uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate, int dw_bias) {
+    const uint32_t *w1, uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate, int dw_bias,
+    const SegBatch *segb, const uint32_t *segt) {
+  static_assert(!(SEG && W), "digit ranges of unweighted tables only");
   using S = LocalLds<K, W, V>;
   constexpr int NT = S::NT, NW = S::NW, SLOTS = S::SLOTS;
   constexpr uint32_t EMPTY = 0xffffffffu;
@@ -1631,9 +1856,23 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
   const Batch none = {0, 0, 0};
   Batch prev = none;  // the previous batch: written out once this batch's keys are in
   uint32_t prev_nu = 0;
-  Batch nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
-  load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
-  uint32_t nd2 = desc_lane_load(batches, blockIdx.x + G, n_batches);
+  Batch nxt;
+  uint32_t nd2;
+  uint32_t nt2 = 0;  // SEG: the segment table read with nd2
+  if constexpr (SEG) {
+    nxt = none;
+    if (blockIdx.x < n_batches) {
+      const SegDesc d0 = seg_unpack(seg_lane_load(segb, blockIdx.x, n_batches));
+      nxt = Batch{d0.out, d0.size, 0};
+      load_seg<K, NT, LPT>(d0, tab_lane_load(segt, blockIdx.x, n_batches), b1, pre);
+    }
+    nd2 = seg_lane_load(segb, blockIdx.x + G, n_batches);
+    nt2 = tab_lane_load(segt, blockIdx.x + G, n_batches);
+  } else {
+    nxt = blockIdx.x < n_batches ? batches[blockIdx.x] : none;
+    load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
+    nd2 = desc_lane_load(batches, blockIdx.x + G, n_batches);
+  }
   for (uint64_t bi = blockIdx.x; bi < n_batches; bi += G) {
     const Batch bt = nxt;
     const uint32_t m = bt.size;
@@ -1721,9 +1960,18 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     __syncthreads();
     // the next batch's keys load while this one is sorted (descriptors are read
     // two batches ahead)
-    nxt = desc_unpack(nd2);
-    nd2 = desc_lane_load(batches, bi + 2 * G, n_batches);
-    if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
+    if constexpr (SEG) {
+      const SegDesc nxs = seg_unpack(nd2);
+      const uint32_t tab = nt2;
+      nxt = Batch{nxs.out, nxs.size, 0};
+      nd2 = seg_lane_load(segb, bi + 2 * G, n_batches);
+      nt2 = tab_lane_load(segt, bi + 2 * G, n_batches);
+      if (bi + G < n_batches) load_seg<K, NT, LPT>(nxs, tab, b1, pre);
+    } else {
+      nxt = desc_unpack(nd2);
+      nd2 = desc_lane_load(batches, bi + 2 * G, n_batches);
+      if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
+    }
     K kall_or = 0, kall_and = all_ones<K>();
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
@@ -2224,7 +2472,20 @@ static void launch_local_sort(unsigned grid, hipStream_t st, const Batch *batche
                        reinterpret_cast<uint64_t *>(x1), wt0, wt1, cnts, bits, ctl, gate, bias);
   else
     hipLaunchKernelGGL((k_local_sort<K, W, V>), dim3(grid), dim3(LocalCfg<K, W, V>::NT), 0, st,
-                       batches, n_batches, x0, x1, wt0, wt1, cnts, bits, ctl, gate, bias);
+                       batches, n_batches, x0, x1, wt0, wt1, cnts, bits, ctl, gate, bias,
+                       (const SegBatch *)nullptr, (const uint32_t *)nullptr);
+}
+
+// The digit ranges of a level's in-tile buckets (128-bit keys).
+template <typename K, int V>
+static void launch_seg_sort(unsigned grid, hipStream_t st, const SegBatch *segb,
+                            const uint64_t *n_seg, const uint32_t *segt, K *x0, K *x1,
+                            uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate, int bias) {
+  static_assert(sizeof(K) == 16, "in-tile buckets: 128-bit keys");
+  hipLaunchKernelGGL((k_local_sort<K, false, V, true>), dim3(grid),
+                     dim3(LocalCfg<K, false, V>::NT), 0, st, (const Batch *)nullptr, n_seg, x0,
+                     x1, (const uint32_t *)nullptr, (const uint32_t *)nullptr, cnts, bits, ctl,
+                     gate, bias, segb, segt);
 }
 
 // A grid rounded up to a multiple of the XCD count.
@@ -2275,7 +2536,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   const uint64_t S = A.n_sets;
   const int len = edges ? A.k + 1 : A.k;
   const int bits = 2 * len;
-  const int ev = edges ? 0 : 10;
+  const int ev = edges ? 0 : DBG_STAGE_EVENTS / 2;
   // The node table of a single-set build may be built from the edge endpoints
   // instead of the k-mers; the device picks the route (k_node_path) and the
   // kernels of the other route return at once.  g0 gates the k-mer route.
@@ -2340,14 +2601,29 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     hipLaunchKernelGGL(k_col_apply, dim3(lcol_chunks), dim3(256), 0, st, thist, csum, n_tiles_p,
                        ctl, gate);
   };
+  // The in-tile level (128-bit keys): the first level whose buckets average at
+  // most a quarter of SEG_TILES tiles per read set; its buckets of at most
+  // SEG_TILES tiles are split within their tiles, and their digit ranges are
+  // sorted right after it (before a later level can write buffer 1).
+  int seg_level = -1;
+  if (sizeof(K) == 16 && A.tuning.in_tile) {
+    const uint64_t per_set = (A.max_keys + S - 1) / S;
+    seg_level = 1;
+    for (uint64_t b = per_set >> 8; b > (uint64_t)SEG_TILES * TILE / 4; b >>= 8) ++seg_level;
+  }
+  SegBatch *segb = reinterpret_cast<SegBatch *>(ws + L.segb);
+  uint32_t *segt = reinterpret_cast<uint32_t *>(ws + L.segt);
+  uint64_t *kw0 = reinterpret_cast<uint64_t *>(x0), *kw1 = reinterpret_cast<uint64_t *>(x1);
+  const int key_words = (int)(sizeof(K) / 8);
   PlanArgs pa{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
-              uniform, L.item_cap, ctl, cap_u, bits, g0};
+              uniform, L.item_cap, ctl, cap_u, bits, g0, seg_level == 1 ? 1 : 0, segb, segt, L.seg_cap,
+              kw0, kw1, key_words, thist};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
   const unsigned level_grid = (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, 8192));
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
   LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], thist, cursor, wt0,
-                wt1, titem, bits, 0, 1};
+                wt1, titem, thist, bits, 0, 1};
   const unsigned plan_grid = grid_for(L.item_cap, 1, 8192);
   if (two_routes) {
     hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, st, ctl, items[0], hist[0]);
@@ -2358,7 +2634,8 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     // (the records' tile rows were written by k_records)
     level_prefix(&ctl->level_tiles[0], 1);
     PlanArgs pw{items[1], &ctl->items[1], hist[1], L.item_cap, batches, L.batch_cap,
-                uniform, L.item_cap, ctl, cap_w, bits, 1};
+                uniform, L.item_cap, ctl, cap_w, bits, 1, 0, segb, segt, L.seg_cap,
+                kw0, kw1, key_words, thist};
     hipLaunchKernelGGL(k_level_plan, dim3(plan_grid), dim3(STREAM_NT), 0, st, pw, la0);
   }
   stage(ev + 3, st);
@@ -2372,6 +2649,12 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     hipLaunchKernelGGL((k_level_scatter<K, true>), dim3(level_grid), dim3(STREAM_NT), 0, st, la0,
                        x0, x1, ctl);
   stage(ev + 4, st);
+  // the run bitmap starts clear (the digit ranges of the in-tile level mark it
+  // inside the level loop)
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.rle_tiles * (TILE / 64), 256, 8192)), dim3(256), 0,
+                     st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
+  const int bias = A.tuning.lds_digit_bias;
+  bool seg_done = false;
   for (int lev = 1; bits - 8 * lev > 0; ++lev) {
     const int li = lev & 1;
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[li], &ctl->items[li],
@@ -2381,15 +2664,20 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     // levels >= 1 split many buckets at once (at least one per set and top
     // digit), so their atomics spread over many counters: atomic mode
     LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li], hist[li], nullptr, cursor,
-                 wt0, wt1, titem, bits, lev, -1};
+                 wt0, wt1, titem, thist, bits, lev, -1};
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
+    if (lev == seg_level)
+      hipLaunchKernelGGL(k_level_tiles<K>, dim3(level_grid), dim3(tiles_nt<K>()), 0, st, la, x0,
+                         x1, ctl);
     PlanArgs pl{items[li ^ 1], &ctl->items[li ^ 1], hist[li ^ 1], L.item_cap, batches,
-                L.batch_cap, uniform, L.item_cap, ctl, cap_u, bits, g0};
+                L.batch_cap, uniform, L.item_cap, ctl, cap_u, bits, g0,
+                lev + 1 == seg_level ? 1 : 0, segb, segt, L.seg_cap, kw0, kw1, key_words, thist};
     hipLaunchKernelGGL(k_level_plan, dim3(plan_grid), dim3(STREAM_NT), 0, st, pl, la);
     if (two_routes) {
       PlanArgs pw = pl;
       pw.local_cap = cap_w;
       pw.gate = 1;
+      pw.in_tile_ok = 0;
       hipLaunchKernelGGL(k_level_plan, dim3(plan_grid), dim3(STREAM_NT), 0, st, pw, la);
     }
     la.gate = g0;
@@ -2400,11 +2688,28 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
       hipLaunchKernelGGL((k_level_scatter<K, true>), dim3(level_grid), dim3(STREAM_NT), 0, st, la,
                          x0, x1, ctl);
     }
+    if (lev == seg_level) {
+      stage(ev + 5, st);
+      if constexpr (sizeof(K) == 16) {
+        if (lv == 0)
+          launch_seg_sort<K, 0>(256, st, segb, &ctl->n_seg, segt, x0, x1, cnts, runbits, ctl,
+                                g0, bias);
+        else if (lv == 1)
+          launch_seg_sort<K, 1>(512, st, segb, &ctl->n_seg, segt, x0, x1, cnts, runbits, ctl,
+                                g0, bias);
+        else
+          launch_seg_sort<K, 2>(256, st, segb, &ctl->n_seg, segt, x0, x1, cnts, runbits, ctl,
+                                g0, bias);
+      }
+      stage(ev + 6, st);
+      seg_done = true;
+    }
   }
-  stage(ev + 5, st);
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.rle_tiles * (TILE / 64), 256, 8192)), dim3(256), 0,
-                     st, reinterpret_cast<uint64_t *>(runbits), L.rle_tiles * (TILE / 64), 0ull);
-  const int bias = A.tuning.lds_digit_bias;
+  if (!seg_done) {
+    stage(ev + 5, st);
+    stage(ev + 6, st);
+  }
+  stage(ev + 7, st);
   if (lv == 0) {
     launch_local_sort<K, false, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, cnts,
                                    runbits, ctl, g0, bias);
@@ -2424,7 +2729,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
       launch_local_sort<K, true, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
                                     cnts, runbits, ctl, 1, bias);
   }
-  stage(ev + 6, st);
+  stage(ev + 8, st);
   hipLaunchKernelGGL(k_uniform_emit<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
                      x1, cnts, runbits, ctl, g0);
   if (two_routes)
@@ -2434,7 +2739,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                      rle_heads, ctl);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, rle_heads, L.rle_tiles,
                      &ctl->n_unique);
-  stage(ev + 7, st);
+  stage(ev + 9, st);
   OutArgs oa{};
   oa.k = A.k;
   uint64_t capacity;
@@ -2457,11 +2762,11 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
     hipLaunchKernelGGL((k_emit_write<K, false>), dim3((unsigned)xcd_grid(L.rle_tiles)),
                        dim3(EMIT_WNT), 0, st, runbits, rle_heads, x0, cnts, oa, L.rle_tiles, ctl);
   }
-  stage(ev + 8, st);
+  stage(ev + 10, st);
   hipLaunchKernelGGL(k_set_rows, dim3(grid_for(S + 1, 256, 1u << 30)), dim3(256), 0, st, runbits,
                      rle_heads, set_kbase, S, set_rows, ctl);
   hipLaunchKernelGGL(k_table_done, dim3(1), dim3(1), 0, st, ctl, edges ? 1 : 0, capacity);
-  stage(ev + 9, st);
+  stage(ev + 11, st);
   return hipGetLastError();
 }
 

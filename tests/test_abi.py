@@ -88,8 +88,9 @@ def test_tuning_round_trip(lib):
     from paper_1003_1940_amd import api
     d = api.set_tuning(defaults=True)
     assert d == {"node_path": api.NODES_AUTO, "endpoint_ratio": pytest.approx(0.6),
-                 "local_variant": 2, "lds_digit_bias": 0}
+                 "local_variant": 2, "lds_digit_bias": 0, "in_tile": 1}
     assert api.set_tuning(local_variant=1, lds_digit_bias=-2)["local_variant"] == 1
+    assert api.set_tuning(in_tile=0)["in_tile"] == 0
     assert api.get_tuning()["lds_digit_bias"] == -2
     api.set_tuning(defaults=True)
     assert api.set_tuning(node_path=api.NODES_ENDPOINTS)["node_path"] == api.NODES_ENDPOINTS
@@ -97,7 +98,8 @@ def test_tuning_round_trip(lib):
     assert api.get_tuning()["node_path"] == api.NODES_ENDPOINTS  # unnamed field kept
     for bad in (dict(node_path=2), dict(node_path=-2), dict(endpoint_ratio=-0.1),
                 dict(endpoint_ratio=3.0), dict(local_variant=3), dict(local_variant=-1),
-                dict(lds_digit_bias=4), dict(lds_digit_bias=-4)):
+                dict(lds_digit_bias=4), dict(lds_digit_bias=-4), dict(in_tile=2),
+                dict(in_tile=-1)):
         with pytest.raises(api.DbgError):
             api.set_tuning(**bad)
     assert api.get_tuning()["endpoint_ratio"] == pytest.approx(0.25)  # refused: unchanged

@@ -12,6 +12,9 @@ def test_candidates_cover_every_knob():
     assert {x["node_path"] for x in c} == {api.NODES_KMERS, api.NODES_ENDPOINTS}
     assert {x["local_variant"] for x in c} == {0, 1, 2}
     assert {x["lds_digit_bias"] for x in c} == {-1, 0, 1}
+    assert {x["in_tile"] for x in c} == {1}
+    c2 = autotune.candidates(in_tiles=(1, 0))
+    assert len(c2) == 36 and {x["in_tile"] for x in c2} == {0, 1}
 
 
 def test_input_class():

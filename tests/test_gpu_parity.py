@@ -62,6 +62,34 @@ def test_k_sweep(k):
     compare_with_oracle(rs.bases, rs.offsets, k, label="k-sweep")
 
 
+@pytest.mark.parametrize("in_tile", [1, 0])
+@pytest.mark.parametrize("k", [33, 63])
+def test_in_tile_level(k, in_tile):
+    """128-bit keys: buckets of the in-tile level are split within their tiles
+    and sorted as digit ranges.  Beside reads of a random genome, 4,000 copies of
+    one read give in-tile buckets with digit cells too large for one batch
+    (gathered, then split further down to uniform buckets), and 3,100 copies of a
+    poly-A read a bucket too large for the in-tile level (scattered as before,
+    at the same level).  Both settings of the knob give the oracle's tables."""
+    from paper_1003_1940_amd import api
+    rnd = random.Random(900 + k)
+    genome = "".join(rnd.choice("ACGT") for _ in range(50_000))
+    comp = str.maketrans("ACGT", "TGCA")
+    reads = []
+    for _ in range(3000):
+        st = rnd.randrange(0, len(genome) - 150)
+        r = genome[st:st + 150]
+        reads.append(r.translate(comp)[::-1] if rnd.random() < 0.5 else r)
+    reads += [genome[1000:1150]] * 4000 + ["A" * 150] * 3100
+    rnd.shuffle(reads)
+    b, o = _rs(reads)
+    api.set_tuning(in_tile=in_tile)
+    try:
+        compare_with_oracle(b, o, k, label=f"in-tile level (in_tile={in_tile})")
+    finally:
+        api.set_tuning(defaults=True)
+
+
 def test_plain_small_full():
     rs = synth.plain_small()
     _, got, ref = compare_with_oracle(rs.bases, rs.offsets, 31, label="plain_small (10k reads)")
