@@ -1376,7 +1376,7 @@ struct LocalLds {
   uint32_t hist[NW][256];
   uint64_t large[2][CAP / 64 + 1];
   uint64_t mid[CAP / (Cfg::SMALL + 1) + 1];
-  uint32_t nlarge[2], nmid, nuniq, dirty;
+  uint32_t nlarge[2], nmid, nuniq, dirty, hbits;
   K wor[NW];
   K wand[NW];
   uint32_t wsum[NW + 1];
@@ -1408,7 +1408,7 @@ struct SlotLds {
   uint32_t hist[NW][256];
   uint64_t large[2][CAP / 64 + 1];
   uint64_t mid[CAP / (Cfg::SMALL + 1) + 1];
-  uint32_t nlarge[2], nmid, nuniq, dirty;
+  uint32_t nlarge[2], nmid, nuniq, dirty, hbits;
   Key wor[NW];
   Key wand[NW];
   uint32_t wsum[NW + 1];
@@ -1798,6 +1798,21 @@ __device__ __forceinline__ void load_batch(const Batch &b, const K *b0, const K 
   }
 }
 
+// One wave (all lanes active): the highest bit in which the batch's keys differ,
+// from the waves' OR and AND of their keys, into s.hbits.
+template <typename S> __device__ __forceinline__ void publish_high_bit(S &s) {
+  using K = typename S::Key;
+  const uint32_t l = lane_id();
+  K o = 0, a = all_ones<K>();
+  if (l < (uint32_t)S::NW) {
+    o = s.wor[l];
+    a = s.wand[l];
+  }
+  o = wave_or_key(o);
+  a = wave_and_key(a);
+  if (l == 0) s.hbits = (uint32_t)bit_length(o ^ a);
+}
+
 // Claimed slots of a wave appended to the distinct-key list with one atomic.
 template <typename S, int LPT>
 __device__ __forceinline__ void record_claims(S &s, uint32_t claimed, uint32_t ncl,
@@ -1915,6 +1930,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     for (uint32_t q = tid; q < (uint32_t)(NW * 256); q += NT) s.hist[0][q] = 0;
     __syncthreads();
     if (tid == 0) s.dirty = 0;
+    if (w == 0) publish_high_bit(s);  // read after the barrier that ends the merge
     // 2. count duplicates in an LDS hash table keyed by the first occurrence:
     //    first probe of every key of this thread at once (independent LDS
     //    atomics in flight), then the keys that own the probed slots (again all
@@ -1972,13 +1988,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
       nd2 = desc_lane_load(batches, bi + 2 * G, n_batches);
       if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
     }
-    K kall_or = 0, kall_and = all_ones<K>();
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      kall_or |= s.wor[i];
-      kall_and &= s.wand[i];
-    }
-    const int hb = bit_length(kall_or ^ kall_and);
+    const int hb = (int)s.hbits;
     // 3. distinct keys read from the table into registers through the list of
     //    claimed slots (which are reset for the next batch)
     const uint32_t nu = s.nuniq;
@@ -2060,6 +2070,7 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
     // keys (above) would otherwise also wait for these stores
     if (bi != blockIdx.x) write_batch<S, W>(s, prev, prev_nu, b0, cnts, bits);
     __syncthreads();  // read out before the region is cleared
+    if (w == 0) publish_high_bit(s);  // read after the barrier that ends the merge
     if (s.dirty) {  // uniform: set before the previous batch's last barrier
       uint4 *r4 = reinterpret_cast<uint4 *>(s.r);
       constexpr uint32_t nkey4 = (uint32_t)SLOTS * 8 / 16, ncnt4 = (uint32_t)SLOTS * 4 / 16;
@@ -2118,13 +2129,7 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
     nxt = desc_unpack(nd2);
     nd2 = desc_lane_load(batches, bi + 2 * G, n_batches);
     if (bi + G < n_batches) load_batch<K, W, NT, LPT>(nxt, b0, b1, w0, w1, pre, prew);
-    K kall_or = 0, kall_and = all_ones<K>();
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      kall_or |= s.wor[i];
-      kall_and &= s.wand[i];
-    }
-    const int hb = bit_length(kall_or ^ kall_and);
+    const int hb = (int)s.hbits;
     // 3. distinct keys and counts read out through the list of claimed slots
     const uint32_t nu = s.nuniq;
     K uk[LPT];
