@@ -85,15 +85,30 @@ struct SegBatch {  // digits [da, db) of an in-tile bucket: one segment per tile
   uint32_t size;      // keys in the range
   uint32_t tiles;     // tiles of the bucket
   uint64_t item_off;  // first key of the bucket (its first tile)
-  uint64_t pad;
+  uint32_t range;     // batch_src(0, level, da, db)
+  uint32_t pad;
 };
 // Beside every SegBatch, a table of SEG_TILES words: word i = the range's
 // first and end offsets inside tile i (each at most TILE, 16 bits apiece).
 
 struct Batch {  // consecutive small buckets [off, off + size) of buffer `src`
   uint64_t off;
-  uint32_t size, src;
+  uint32_t size;
+  uint32_t src;  // batch_src: the buffer, and the digit range the buckets span
 };
+
+// A batch's buckets are the children [da, db) of one parent split by the digit
+// of partition level `level`: its keys share every bit above that digit and the
+// digit lies in [da, db).  Packed with the buffer into Batch::src (and into
+// SegBatch::range): bit 0 buffer, bits 1..5 level + 1 (0: no range known),
+// bits 6..13 da, bits 14..22 db.
+__host__ __device__ inline uint32_t batch_src(uint32_t buf, int level, uint32_t da, uint32_t db) {
+  return buf | (uint32_t)(level + 1) << 1 | da << 6 | db << 14;
+}
+__host__ __device__ inline uint32_t batch_buf(uint32_t src) { return src & 1u; }
+__host__ __device__ inline int batch_level(uint32_t src) { return (int)((src >> 1) & 31u) - 1; }
+__host__ __device__ inline uint32_t batch_da(uint32_t src) { return (src >> 6) & 0xffu; }
+__host__ __device__ inline uint32_t batch_db(uint32_t src) { return (src >> 14) & 0x1ffu; }
 
 // Byte layout of a caller-provided workspace.
 struct Layout {

@@ -928,11 +928,14 @@ __device__ void plan_children(const PlanArgs &p, uint64_t c, uint64_t off, uint3
   if (d < nb) {
     const uint64_t bi = s.base[0] + d;
     if (!sp) {
-      if (bi < p.batch_cap) p.batches[bi] = Batch{off + s.ex[s.bchild[d]], s.bsize[d], src};
+      if (bi < p.batch_cap)
+        p.batches[bi] = Batch{off + s.ex[s.bchild[d]], s.bsize[d],
+                              batch_src(src, child_level - 1, s.bchild[d], s.blast[d] + 1)};
       else set_status(p.ctl, DBG_E_INTERNAL);
     } else {
       if (bi < p.seg_cap)
-        p.segb[bi] = SegBatch{off + s.ex[s.bchild[d]], s.bsize[d], sp->tiles, off, 0};
+        p.segb[bi] = SegBatch{off + s.ex[s.bchild[d]], s.bsize[d], sp->tiles, off,
+                              batch_src(0, child_level - 1, s.bchild[d], s.blast[d] + 1), 0};
       else set_status(p.ctl, DBG_E_INTERNAL);
     }
   }
@@ -1519,7 +1522,7 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
                                              const uint32_t (&uc)[UPT], uint32_t nu, int hb,
                                              int dw_bias, const Batch &bt,
                                              typename S::Key *b0, uint32_t *cnts,
-                                             uint32_t *bits) {
+                                             uint32_t *bits, int key_bits) {
   using K = typename S::Key;
   using CT = typename S::CT;
   constexpr int NT = S::NT, NW = S::NW;
@@ -1533,19 +1536,40 @@ __device__ __forceinline__ void finish_batch(S &s, const typename S::Key (&uk)[U
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   K *key0 = s.k0();
   CT *cnt0 = s.c0();
-  // digit width: about one distinct key per bucket (shifted by the tuning's
-  // bias), at most MAXDW bits, taken just below hb
-  int dw = (nu <= 256 ? 8 : bit_length((uint64_t)(nu - 1))) + dw_bias;
-  dw = dw < 1 ? 1 : dw > MAXDW ? MAXDW : dw;
-  dw = dw > hb ? hb : dw;
-  const int dshift = hb - dw;
+  // digit of the first partition: about one distinct key per bucket (shifted
+  // by the tuning's bias), at most MAXDW bits, taken just below hb.  When the
+  // keys differ inside the digit of the level that made the batch (they share
+  // every bit above it, and it lies in [da, db)), the bins are (digit - da)
+  // followed by the bits below it instead: that digit takes only db - da
+  // values, so the bits just below hb would leave most bins empty and crowd
+  // the rest.
+  int dw, dshift;
+  uint32_t dsub = 0;
+  const int lvl = batch_level(bt.src);
+  const int dhi = key_bits - 8 * lvl;  // the level's digit: bits [dpos, dhi)
+  const int dpos = dhi - 8 > 0 ? dhi - 8 : 0;
+  if (lvl >= 0 && hb > dpos && hb <= dhi) {
+    const uint32_t da = batch_da(bt.src), range = batch_db(bt.src) - da;
+    const int rbits = bit_length((uint64_t)(range - 1));
+    int x = MAXDW - rbits + dw_bias;
+    const int xmax = MAXDW - rbits < dpos ? MAXDW - rbits : dpos;
+    x = x < 0 ? 0 : x > xmax ? xmax : x;
+    dw = dhi - dpos + x;
+    dshift = dpos - x;
+    dsub = da << x;
+  } else {
+    dw = (nu <= 256 ? 8 : bit_length((uint64_t)(nu - 1))) + dw_bias;
+    dw = dw < 1 ? 1 : dw > MAXDW ? MAXDW : dw;
+    dw = dw > hb ? hb : dw;
+    dshift = hb - dw;
+  }
   uint32_t *H = &s.hist[0][0];  // NW * 256 bins, zeroed by the caller
   uint32_t ud[UPT];
 #pragma unroll
   for (int j = 0; j < UPT; ++j) {
     ud[j] = 0;
     if (tid + (uint32_t)j * NT < nu) {
-      ud[j] = dw > 0 ? (uint32_t)shr<K>(uk[j], dshift) & ((1u << dw) - 1u) : 0u;
+      ud[j] = dw > 0 ? ((uint32_t)shr<K>(uk[j], dshift) & ((1u << dw) - 1u)) - dsub : 0u;
       atomicAdd(&H[ud[j]], 1u);
     }
   }
@@ -1709,7 +1733,7 @@ __device__ __forceinline__ Batch desc_unpack(uint32_t v) {
 // l), as desc_lane_load.
 struct SegDesc {
   uint64_t out, item_off;
-  uint32_t size, tiles;
+  uint32_t size, tiles, range;
 };
 // The lane index made opaque where it is used, so that per-lane addresses are
 // formed in the loop rather than kept live across it (they were spilled, and
@@ -1732,7 +1756,8 @@ __device__ __forceinline__ uint32_t tab_lane_load(const uint32_t *segt, uint64_t
 }
 __device__ __forceinline__ SegDesc seg_unpack(uint32_t v) {
   auto rl = [&](int l) { return (uint32_t)__builtin_amdgcn_readlane(v, l); };
-  return SegDesc{((uint64_t)rl(1) << 32) | rl(0), ((uint64_t)rl(5) << 32) | rl(4), rl(2), rl(3)};
+  return SegDesc{((uint64_t)rl(1) << 32) | rl(0), ((uint64_t)rl(5) << 32) | rl(4), rl(2), rl(3),
+                 rl(6)};
 }
 // Keys of a digit range into registers (key e = tid + j NT as load_batch): the
 // range is the concatenation of its segments in tile order (lane l < tiles holds
@@ -1782,14 +1807,14 @@ template <typename K, bool W, int NT, int LPT>
 __device__ __forceinline__ void load_batch(const Batch &b, const K *b0, const K *b1,
                                            const uint32_t *w0, const uint32_t *w1,
                                            K (&pre)[LPT], uint32_t (&prew)[W ? LPT : 1]) {
-  const K *src = b.src ? b1 : b0;
+  const K *src = batch_buf(b.src) ? b1 : b0;
 #pragma unroll
   for (int j = 0; j < LPT; ++j) {
     const uint32_t e = threadIdx.x + (uint32_t)j * NT;
     pre[j] = e < b.size ? src[b.off + e] : K(0);
   }
   if (W) {
-    const uint32_t *srcw = b.src ? w1 : w0;
+    const uint32_t *srcw = batch_buf(b.src) ? w1 : w0;
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
       const uint32_t e = threadIdx.x + (uint32_t)j * NT;
@@ -1848,7 +1873,7 @@ template <typename K, bool W, int V, bool SEG = false>
 __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     const Batch *batches, const uint64_t *n_batches_p, K *b0, K *b1, const uint32_t *w0,
     const uint32_t *w1, uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate, int dw_bias,
-    const SegBatch *segb, const uint32_t *segt) {
+    int key_bits, const SegBatch *segb, const uint32_t *segt) {
   static_assert(!(SEG && W), "digit ranges of unweighted tables only");
   using S = LocalLds<K, W, V>;
   constexpr int NT = S::NT, NW = S::NW, SLOTS = S::SLOTS;
@@ -1878,7 +1903,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     nxt = none;
     if (blockIdx.x < n_batches) {
       const SegDesc d0 = seg_unpack(seg_lane_load(segb, blockIdx.x, n_batches));
-      nxt = Batch{d0.out, d0.size, 0};
+      nxt = Batch{d0.out, d0.size, d0.range};
       load_seg<K, NT, LPT>(d0, tab_lane_load(segt, blockIdx.x, n_batches), b1, pre);
     }
     nd2 = seg_lane_load(segb, blockIdx.x + G, n_batches);
@@ -1979,7 +2004,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
     if constexpr (SEG) {
       const SegDesc nxs = seg_unpack(nd2);
       const uint32_t tab = nt2;
-      nxt = Batch{nxs.out, nxs.size, 0};
+      nxt = Batch{nxs.out, nxs.size, nxs.range};
       nd2 = seg_lane_load(segb, bi + 2 * G, n_batches);
       nt2 = tab_lane_load(segt, bi + 2 * G, n_batches);
       if (bi + G < n_batches) load_seg<K, NT, LPT>(nxs, tab, b1, pre);
@@ -2007,7 +2032,7 @@ __global__ __launch_bounds__((LocalCfg<K, W, V>::NT)) void k_local_sort(
         tcnt[q] = 0;
       }
     }
-    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, cnts, bits);
+    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, cnts, bits, key_bits);
     prev = bt;
     prev_nu = nu;
   }
@@ -2018,7 +2043,7 @@ template <bool W, int V>
 __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdgpu_waves_per_eu(LocalCfg<uint64_t, W, V>::WAVES_PER_EU))) void k_local_sort64(
     const Batch *batches, const uint64_t *n_batches_p, uint64_t *b0, uint64_t *b1,
     const uint32_t *w0, const uint32_t *w1, uint32_t *cnts, uint32_t *bits, const Ctl *ctl,
-    int gate, int dw_bias) {
+    int gate, int dw_bias, int key_bits) {
   using S = SlotLds<W, V>;
   using K = uint64_t;
   constexpr int NT = S::NT, NW = S::NW, SLOTS = S::SLOTS;
@@ -2147,7 +2172,7 @@ __global__ __launch_bounds__((LocalCfg<uint64_t, W, V>::NT)) __attribute__((amdg
         tcnt[q] = 0;
       }
     }
-    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, cnts, bits);
+    finish_batch<S, W, LPT, true>(s, uk, uc, nu, hb, dw_bias, bt, b0, cnts, bits, key_bits);
     prev_nu = nu;
     prev = bt;
   }
@@ -2470,27 +2495,29 @@ template <typename K, bool W, int V>
 static void launch_local_sort(unsigned grid, hipStream_t st, const Batch *batches,
                               const uint64_t *n_batches, K *x0, K *x1, const uint32_t *wt0,
                               const uint32_t *wt1, uint32_t *cnts, uint32_t *bits,
-                              const Ctl *ctl, int gate, int bias) {
+                              const Ctl *ctl, int gate, int bias, int key_bits) {
   if constexpr (sizeof(K) == 8)
     hipLaunchKernelGGL((k_local_sort64<W, V>), dim3(grid), dim3(LocalCfg<K, W, V>::NT), 0, st,
                        batches, n_batches, reinterpret_cast<uint64_t *>(x0),
-                       reinterpret_cast<uint64_t *>(x1), wt0, wt1, cnts, bits, ctl, gate, bias);
+                       reinterpret_cast<uint64_t *>(x1), wt0, wt1, cnts, bits, ctl, gate, bias,
+                       key_bits);
   else
     hipLaunchKernelGGL((k_local_sort<K, W, V>), dim3(grid), dim3(LocalCfg<K, W, V>::NT), 0, st,
                        batches, n_batches, x0, x1, wt0, wt1, cnts, bits, ctl, gate, bias,
-                       (const SegBatch *)nullptr, (const uint32_t *)nullptr);
+                       key_bits, (const SegBatch *)nullptr, (const uint32_t *)nullptr);
 }
 
 // The digit ranges of a level's in-tile buckets (128-bit keys).
 template <typename K, int V>
 static void launch_seg_sort(unsigned grid, hipStream_t st, const SegBatch *segb,
                             const uint64_t *n_seg, const uint32_t *segt, K *x0, K *x1,
-                            uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate, int bias) {
+                            uint32_t *cnts, uint32_t *bits, const Ctl *ctl, int gate, int bias,
+                            int key_bits) {
   static_assert(sizeof(K) == 16, "in-tile buckets: 128-bit keys");
   hipLaunchKernelGGL((k_local_sort<K, false, V, true>), dim3(grid),
                      dim3(LocalCfg<K, false, V>::NT), 0, st, (const Batch *)nullptr, n_seg, x0,
                      x1, (const uint32_t *)nullptr, (const uint32_t *)nullptr, cnts, bits, ctl,
-                     gate, bias, segb, segt);
+                     gate, bias, key_bits, segb, segt);
 }
 
 // A grid rounded up to a multiple of the XCD count.
@@ -2698,13 +2725,13 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
       if constexpr (sizeof(K) == 16) {
         if (lv == 0)
           launch_seg_sort<K, 0>(256, st, segb, &ctl->n_seg, segt, x0, x1, cnts, runbits, ctl,
-                                g0, bias);
+                                g0, bias, bits);
         else if (lv == 1)
           launch_seg_sort<K, 1>(512, st, segb, &ctl->n_seg, segt, x0, x1, cnts, runbits, ctl,
-                                g0, bias);
+                                g0, bias, bits);
         else
           launch_seg_sort<K, 2>(256, st, segb, &ctl->n_seg, segt, x0, x1, cnts, runbits, ctl,
-                                g0, bias);
+                                g0, bias, bits);
       }
       stage(ev + 6, st);
       seg_done = true;
@@ -2717,22 +2744,22 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   stage(ev + 7, st);
   if (lv == 0) {
     launch_local_sort<K, false, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, cnts,
-                                   runbits, ctl, g0, bias);
+                                   runbits, ctl, g0, bias, bits);
     if (two_routes)
       launch_local_sort<K, true, 0>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
-                                    cnts, runbits, ctl, 1, bias);
+                                    cnts, runbits, ctl, 1, bias, bits);
   } else if (lv == 1) {
     launch_local_sort<K, false, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, cnts,
-                                   runbits, ctl, g0, bias);
+                                   runbits, ctl, g0, bias, bits);
     if (two_routes)
       launch_local_sort<K, true, 1>(512, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
-                                    cnts, runbits, ctl, 1, bias);
+                                    cnts, runbits, ctl, 1, bias, bits);
   } else {
     launch_local_sort<K, false, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1, cnts,
-                                   runbits, ctl, g0, bias);
+                                   runbits, ctl, g0, bias, bits);
     if (two_routes)
       launch_local_sort<K, true, 2>(256, st, batches, &ctl->n_batches, x0, x1, wt0, wt1,
-                                    cnts, runbits, ctl, 1, bias);
+                                    cnts, runbits, ctl, 1, bias, bits);
   }
   stage(ev + 8, st);
   hipLaunchKernelGGL(k_uniform_emit<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform, x0,
