@@ -114,20 +114,28 @@ def run_copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def run_cpu_baseline(rs, k, target_s=15.0):
-    """The oracle, as is, on a bounded prefix of the reads (host cores)."""
+def run_cpu_baseline(rs, k, target_s=12.0):
+    """The oracle, as is, on a bounded prefix of the reads (host cores): prefixes
+    grow until one takes a second or more, then one prefix sized for about
+    target_s seconds is timed."""
     import oracle
     oracle.build(force=False)
     threads = oracle.host_threads(0)
     n = 2000
-    while True:
-        sub = rs.subset(np.arange(min(n, rs.n_reads)))
+
+    def timed(n_):
+        sub_ = rs.subset(np.arange(min(n_, rs.n_reads)))
         t0 = time.perf_counter()
-        oracle.build_graph(sub.bases, sub.offsets, k, threads=threads)
-        dt = time.perf_counter() - t0
-        if dt >= target_s / 4 or n >= rs.n_reads:
+        oracle.build_graph(sub_.bases, sub_.offsets, k, threads=threads)
+        return sub_, time.perf_counter() - t0
+
+    while True:
+        sub, dt = timed(n)
+        if dt >= 1.0 or n >= rs.n_reads:
             break
-        n = int(min(rs.n_reads, n * max(2.0, min(8.0, target_s / 2 / max(dt, 1e-3)))))
+        n = int(min(rs.n_reads, n * max(2.0, min(8.0, 1.5 / max(dt, 1e-3)))))
+    if n < rs.n_reads:
+        sub, dt = timed(int(min(rs.n_reads, n * target_s / dt)))
     kmers = sub.kmer_count(k)
     return {"value": kmers / dt, "unit": "k-mers/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sub.n_reads} reads of the workload ({kmers} k-mer positions), "

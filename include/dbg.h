@@ -181,7 +181,10 @@ int dbg_build_batched(const uint64_t *packed, uint64_t n_bases, const uint64_t *
                       size_t workspace_bytes, hipStream_t stream);
 
 /* Pack ASCII bases (device, n_bases bytes of A/C/G/T, either case) into the
- * 2-bit stream (device, ceil(n_bases / 32) words; bits past the last base are 0).
+ * 2-bit stream (device, ceil(n_bases / 32) words; bits past the last base are 0):
+ * the reads are strings over the four-letter DNA alphabet of Sec. 1 and Sec. 2,
+ * coded A=0, C=1, G=2, T=3 so that numeric order is the lexicographic order of
+ * Fig. 2 (the canonical k-mer is the smaller of the pair in that order).
  * A byte outside {A,C,G,T,a,c,g,t} sets result->status = DBG_E_BASE (result is
  * device memory; its other fields are untouched). */
 int dbg_pack_ascii(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed,

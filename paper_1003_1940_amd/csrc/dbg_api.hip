@@ -95,6 +95,7 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
   L.segt = take(L.seg_cap * SEG_TILES * sizeof(uint32_t));
   L.uniform = take(L.item_cap * sizeof(Item));
   L.rle_heads = take(L.rle_tiles * sizeof(uint64_t));
+  L.rle_sums = take((L.rle_tiles / 4096 + 2) * sizeof(uint64_t));
   L.bits = take(L.rle_tiles * (TILE / 8));
   // the count of each distinct key, at the key's position in buffer 0
   L.counts = take((max_keys + 2) * sizeof(uint32_t));

@@ -117,6 +117,7 @@ struct Layout {
   size_t counts;  // uint32 count of each distinct key, beside buffer 0
   size_t segb;    // SegBatch list of the in-tile level
   size_t segt;    // their segment tables, SEG_TILES words each
+  size_t rle_sums;  // chunk sums of the per-tile distinct counts
   size_t titem;   // uint32 item of every tile of a partition level
   size_t keys[2];
   size_t weights;  // byte offset of the record weights inside each key buffer

@@ -166,6 +166,39 @@ __global__ __launch_bounds__(1024) void k_scan_small(uint64_t *a, uint64_t n, ui
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// Exclusive scan of a long u64 array in three launches: chunk sums
+// (k_chunk_reduce), a scan of those (k_scan_small), each chunk scanned from its
+// offset (k_chunk_apply).  A chunk is SCAN_TILE entries.
+__global__ __launch_bounds__(SCAN_NT) void k_chunk_reduce(const uint64_t *a, uint64_t n,
+                                                          uint64_t *csum) {
+  __shared__ uint64_t wsum[SCAN_NT / 64 + 1];
+  const uint64_t i0 = blockIdx.x * SCAN_TILE + threadIdx.x * (uint64_t)SCAN_PT;
+  uint64_t s = 0;
+#pragma unroll
+  for (int r = 0; r < SCAN_PT; ++r) s += i0 + r < n ? a[i0 + r] : 0;
+  uint64_t tot;
+  block_exclusive_scan<SCAN_NT>(s, wsum, &tot);
+  if (threadIdx.x == 0) csum[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(SCAN_NT) void k_chunk_apply(uint64_t *a, uint64_t n,
+                                                         const uint64_t *csum) {
+  __shared__ uint64_t wsum[SCAN_NT / 64 + 1];
+  const uint64_t i0 = blockIdx.x * SCAN_TILE + threadIdx.x * (uint64_t)SCAN_PT;
+  uint64_t v[SCAN_PT], s = 0;
+#pragma unroll
+  for (int r = 0; r < SCAN_PT; ++r) {
+    v[r] = i0 + r < n ? a[i0 + r] : 0;
+    s += v[r];
+  }
+  uint64_t tot;
+  uint64_t ex = block_exclusive_scan<SCAN_NT>(s, wsum, &tot) + csum[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < SCAN_PT; ++r) {
+    if (i0 + r < n) a[i0 + r] = ex;
+    ex += v[r];
+  }
+}
+
 __global__ __launch_bounds__(SCAN_NT) void k_read_apply(const uint64_t *off, uint64_t n_reads,
                                                         int len, const uint64_t *block_sums,
                                                         uint64_t *rbase, Ctl *ctl) {
@@ -2769,8 +2802,15 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                        x0, x1, wt0, wt1, cnts, runbits, ctl, 1);
   hipLaunchKernelGGL(k_emit_count, dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st, runbits,
                      rle_heads, ctl);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, rle_heads, L.rle_tiles,
-                     &ctl->n_unique);
+  {
+    const uint64_t nch = (L.rle_tiles + SCAN_TILE - 1) / SCAN_TILE;
+    uint64_t *rle_sums = reinterpret_cast<uint64_t *>(ws + L.rle_sums);
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((unsigned)nch), dim3(SCAN_NT), 0, st, rle_heads,
+                       L.rle_tiles, rle_sums);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, rle_sums, nch, &ctl->n_unique);
+    hipLaunchKernelGGL(k_chunk_apply, dim3((unsigned)nch), dim3(SCAN_NT), 0, st, rle_heads,
+                       L.rle_tiles, rle_sums);
+  }
   stage(ev + 9, st);
   OutArgs oa{};
   oa.k = A.k;
