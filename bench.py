@@ -768,7 +768,10 @@ def _segment(dispatches):
             continue
         if s.endswith("k_table_reset"):
             tbl = "edges" if tbl is None else "nodes"
-        if tbl is not None and not s.endswith("k_write_result"):
+        if s.endswith("k_write_result"):  # a build's last kernel: what follows is not
+            cur = None                      # part of it (graph kernels timed after it)
+            continue
+        if tbl is not None:
             cur[tbl].append((s, val))
     return builds
 

@@ -58,6 +58,7 @@ struct Ctl {
   uint64_t n_tiles;         // enumeration tiles of that table
   uint64_t items[2];        // oversized buckets waiting for the next level (two lists)
   uint64_t level_tiles[2];  // 4096-key tiles over each list's buckets
+  uint64_t level_scatter_tiles[2];  // the first ones: tiles of buckets that are scattered
   uint64_t n_batches;       // batches of small buckets for the LDS sort
   uint64_t n_uniform;       // oversized buckets whose digits are exhausted (all keys equal)
   uint64_t n_unique;        // distinct keys of the table

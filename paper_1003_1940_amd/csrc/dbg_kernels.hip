@@ -81,6 +81,7 @@ __global__ void k_table_reset(Ctl *ctl) {
     ctl->n_tiles = 0;
     ctl->items[0] = ctl->items[1] = 0;
     ctl->level_tiles[0] = ctl->level_tiles[1] = 0;
+    ctl->level_scatter_tiles[0] = ctl->level_scatter_tiles[1] = 0;
     ctl->n_batches = 0;
     ctl->n_uniform = 0;
     ctl->n_unique = 0;
@@ -1039,24 +1040,33 @@ __global__ __launch_bounds__(STREAM_NT) void k_set_plan(PlanArgs p, const uint32
 // ---------------------------------------------------------------------------
 // 3. Partition levels >= 1 over oversized buckets.
 
-// One workgroup: tile offsets of the items of a list.
+// One workgroup: tile offsets of the items of a list.  The tiles of buckets that
+// are scattered come first, in list order (the tile mode's column prefix needs
+// them so); the tiles of in-tile buckets follow, so that each kernel of a level
+// walks only its own tiles.
 __global__ __launch_bounds__(1024) void k_level_prep(Item *items, const uint64_t *n_items_p,
-                                                     uint64_t *n_tiles_out, uint64_t *other_count,
-                                                     const Ctl *ctl, int gate) {
+                                                     uint64_t *n_tiles_out,
+                                                     uint64_t *n_scatter_tiles_out,
+                                                     uint64_t *other_count, const Ctl *ctl,
+                                                     int gate) {
   __shared__ uint64_t wsum[1024 / 64 + 1];
   if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t n = *n_items_p;
-  uint64_t carry = 0;
-  for (uint64_t c0 = 0; c0 < n; c0 += 1024) {
-    const uint64_t i = c0 + threadIdx.x;
-    const uint64_t tiles = i < n ? (items[i].size + TILE - 1) / TILE : 0;
-    uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<1024>(tiles, wsum, &tot) + carry;
-    if (i < n) items[i].tbase = ex;
-    carry += tot;
+  uint64_t carry[2] = {0, 0};
+  for (int pass = 0; pass < 2; ++pass) {  // 0: scattered buckets, 1: in-tile buckets
+    for (uint64_t c0 = 0; c0 < n; c0 += 1024) {
+      const uint64_t i = c0 + threadIdx.x;
+      const bool mine = i < n && items[i].in_tile == (uint32_t)pass;
+      const uint64_t tiles = mine ? (items[i].size + TILE - 1) / TILE : 0;
+      uint64_t tot;
+      const uint64_t ex = block_exclusive_scan<1024>(tiles, wsum, &tot) + carry[pass];
+      if (mine) items[i].tbase = ex + (pass ? carry[0] : 0);
+      carry[pass] += tot;
+    }
   }
   if (threadIdx.x == 0) {
-    *n_tiles_out = carry;
+    *n_scatter_tiles_out = carry[0];
+    *n_tiles_out = carry[0] + carry[1];
     *other_count = 0;  // the other list receives this level's oversized children
   }
 }
@@ -1076,7 +1086,11 @@ __global__ __launch_bounds__(256) void k_level_tilemap(const Item *items,
   }
   for (uint64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
     const uint64_t t0 = items[ii].tbase;
-    const uint64_t t1 = ii + 1 < n_items ? items[ii + 1].tbase : n_tiles;
+    const uint64_t t1 = t0 + (items[ii].size + TILE - 1) / TILE;
+    if (t1 > n_tiles) {
+      if (threadIdx.x == 0) set_status(ctl, DBG_E_INTERNAL);
+      return;
+    }
     for (uint64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) titem[t] = (uint32_t)ii;
   }
 }
@@ -1085,6 +1099,7 @@ struct LevelArgs {
   const Item *items;
   const uint64_t *n_items_p;
   const uint64_t *n_tiles_p;
+  const uint64_t *n_scatter_tiles_p;  // tiles [0, this) belong to scattered buckets
   uint64_t *hist;     // per-item digit counts (atomic mode)
   uint32_t *tpre;     // per-tile digit counts, then their column prefix (tile mode), or null
   uint64_t *cursor;
@@ -1126,7 +1141,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_hist(LevelArgs a, K *b0, K 
                                                           const Ctl *ctl) {
   __shared__ uint32_t h[256];
   if (ctl->status || gated_off(ctl, a.gate)) return;
-  const uint64_t n_tiles = *a.n_tiles_p;
+  const uint64_t n_tiles = *a.n_scatter_tiles_p;
   // a contiguous run of tiles per workgroup: consecutive tiles mostly share their
   // bucket, whose counts then go out once per run instead of once per tile
   const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
@@ -1206,7 +1221,7 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_scatter(LevelArgs a, K *b0,
   constexpr int NT = STREAM_NT;
   __shared__ PartLds<K, W, 1, NT> s;
   if (ctl->status || gated_off(ctl, a.gate)) return;
-  const uint64_t n_tiles = *a.n_tiles_p, n_items = *a.n_items_p;
+  const uint64_t n_tiles = *a.n_scatter_tiles_p;
   // this XCD's eighth of the tiles, strided over its workgroups (gridDim.x is a
   // multiple of 8)
   const uint64_t per = (n_tiles + N_XCD - 1) / N_XCD;
@@ -1248,7 +1263,7 @@ __global__ __launch_bounds__(tiles_nt<K>()) void k_level_tiles(LevelArgs a, K *b
   __shared__ PartLds<K, false, 1, NT> s;
   if (ctl->status || gated_off(ctl, a.gate)) return;
   const uint64_t n_tiles = *a.n_tiles_p;
-  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  for (uint64_t t = *a.n_scatter_tiles_p + blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint64_t ii = a.titem[t];
     const Item it = a.items[ii];
     if (!it.in_tile) continue;
@@ -2687,13 +2702,13 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                      set_tbase, cursor0, set_kbase, S);
   const unsigned level_grid = (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, 8192));
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
-  LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], hist[0], thist, cursor, wt0,
-                wt1, titem, thist, bits, 0, 1};
+  LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], &ctl->level_scatter_tiles[0],
+                hist[0], thist, cursor, wt0, wt1, titem, thist, bits, 0, 1};
   const unsigned plan_grid = grid_for(L.item_cap, 1, 8192);
   if (two_routes) {
     hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, st, ctl, items[0], hist[0]);
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[0], &ctl->items[0],
-                       &ctl->level_tiles[0], &ctl->items[1], ctl, 1);
+                       &ctl->level_tiles[0], &ctl->level_scatter_tiles[0], &ctl->items[1], ctl, 1);
     hipLaunchKernelGGL(k_level_tilemap, dim3(plan_grid), dim3(256), 0, st, items[0],
                        &ctl->items[0], &ctl->level_tiles[0], titem, titem_cap, ctl, 1);
     // (the records' tile rows were written by k_records)
@@ -2723,13 +2738,15 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   for (int lev = 1; bits - 8 * lev > 0; ++lev) {
     const int li = lev & 1;
     hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(1024), 0, st, items[li], &ctl->items[li],
-                       &ctl->level_tiles[li], &ctl->items[li ^ 1], ctl, -1);
+                       &ctl->level_tiles[li], &ctl->level_scatter_tiles[li], &ctl->items[li ^ 1],
+                       ctl, -1);
     hipLaunchKernelGGL(k_level_tilemap, dim3(plan_grid), dim3(256), 0, st, items[li],
                        &ctl->items[li], &ctl->level_tiles[li], titem, titem_cap, ctl, -1);
     // levels >= 1 split many buckets at once (at least one per set and top
     // digit), so their atomics spread over many counters: atomic mode
-    LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li], hist[li], nullptr, cursor,
-                 wt0, wt1, titem, thist, bits, lev, -1};
+    LevelArgs la{items[li], &ctl->items[li], &ctl->level_tiles[li],
+                 &ctl->level_scatter_tiles[li], hist[li], nullptr, cursor, wt0, wt1, titem, thist,
+                 bits, lev, -1};
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
     if (lev == seg_level)
       hipLaunchKernelGGL(k_level_tiles<K>, dim3(level_grid), dim3(tiles_nt<K>()), 0, st, la, x0,
