@@ -1416,9 +1416,12 @@ struct LocalLds {
   using Cfg = LocalCfg<K, W, V>;
   using CT = typename std::conditional<W, uint32_t, uint16_t>::type;
   static constexpr int NT = Cfg::NT, NW = NT / 64, CAP = Cfg::CAP;
-  static constexpr int SLOTS = Cfg::SLOTS;
-  static constexpr size_t TBYTES_A = (size_t)SLOTS * 8;
+  // the table (an owner index and a count per slot) takes all of the region it
+  // shares with buffer 1: fewer collisions for the same LDS
   static constexpr size_t TBYTES_B = (size_t)CAP * (sizeof(K) + sizeof(CT));
+  static constexpr int SLOTS =
+      (int)((size_t)Cfg::SLOTS * 8 > TBYTES_B ? (size_t)Cfg::SLOTS : TBYTES_B / 8);
+  static constexpr size_t TBYTES_A = (size_t)SLOTS * 8;
   static constexpr size_t TBYTES = TBYTES_A > TBYTES_B ? TBYTES_A : TBYTES_B;
   K key0[CAP];        // staged keys, then distinct keys (sorted in place)
   CT cnt0[CAP];
