@@ -522,11 +522,75 @@ __device__ __forceinline__ int enum_keys_global(const EnumArgs &a, const TileSrc
   return n;
 }
 
+// The staged enumeration without divergence: a thread's KPT consecutive keys
+// meet at most one read start when reads hold at least KPT keys, so every thread
+// computes both seeds up front (its first key's, and the first key's of the read
+// that starts inside its range, if any) and then only rolls, taking the second
+// seed with a select at the step where that read starts.  Returns -1, having
+// written nothing, when some thread of the wave meets two read starts (short
+// reads): the wave then takes enum_keys_staged.
 template <typename K, int KPT>
+__device__ __forceinline__ int enum_keys_two_seeds(const EnumArgs &a, const TileSrc &ts,
+                                                   uint64_t g0, uint64_t g_end, K (&out)[KPT]) {
+  const bool any = g0 < g_end;
+  const uint32_t gl0 = any ? (uint32_t)(g0 - ts.g_base) : 0u;
+  const uint32_t gle = any ? (uint32_t)(g_end - ts.g_base) : 0u;
+  const uint32_t glast = gl0 + (uint32_t)KPT < gle ? gl0 + (uint32_t)KPT : gle;  // range end
+  uint32_t lo = 0, hi = ts.nr - 1;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (ts.lrb[mid] <= gl0) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t next = ts.lrb[lo + 1];  // first key of the following read (> gl0)
+  const bool sw = any && next < glast;
+  uint32_t j = lo + 1;
+  if (sw)
+    while (ts.lrb[j + 1] == next) ++j;  // past reads with no key
+  const bool two = sw && ts.lrb[j + 1] < glast;
+  if (__any(two)) return -1;
+  const int len = a.len;
+  const K mask = low_mask<K>(2 * len);
+  const int top = 2 * len - 2;
+  uint32_t P = ts.loff[lo] + (gl0 - ts.lrb[lo]);
+  const uint32_t P2 = sw ? ts.loff[j] : P;
+  const uint32_t rs = sw ? next - gl0 : (uint32_t)KPT;  // step that starts the new read
+  K fw = extract_staged(ts.lw, P, len, K());
+  K rc = revcomp(fw, len);
+  const K fw2 = extract_staged(ts.lw, P2, len, K());
+  const K rc2 = revcomp(fw2, len);
+  int n = 0;
+#pragma unroll
+  for (int r = 0; r < KPT; ++r) {
+    if (r > 0) {
+      const uint32_t q = P + (uint32_t)len;
+      const uint32_t c = (uint32_t)(ts.lw[q >> 5] >> (62 - 2 * (int)(q & 31))) & 3u;
+      const bool now = (uint32_t)r == rs;
+      fw = now ? fw2 : (((fw << 2) | (K)c) & mask);
+      rc = now ? rc2 : ((rc >> 2) | ((K)(3u - c) << top));
+      P = now ? P2 : P + 1;
+    }
+    if (gl0 + (uint32_t)r < glast) {
+      out[r] = rc < fw ? rc : fw;
+      ++n;
+    }
+  }
+  return n;
+}
+
+// TWO: try the two-seed form first (the histogram pass; in the scatter pass its
+// extra registers cost more occupancy than its divergence saves: measured).
+template <typename K, int KPT, bool TWO = false>
 __device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, uint64_t g0,
                                          uint64_t g_end, uint64_t read_lo, uint64_t read_hi,
                                          K (&out)[KPT]) {
-  if (ts.fast) return enum_keys_staged<K, KPT>(a, ts, g0, g_end, out);
+  if (ts.fast) {
+    if constexpr (TWO) {
+      const int n = enum_keys_two_seeds<K, KPT>(a, ts, g0, g_end, out);
+      if (n >= 0) return n;
+    }
+    return enum_keys_staged<K, KPT>(a, ts, g0, g_end, out);
+  }
   return enum_keys_global<K, KPT>(a, ts, g0, g_end, read_lo, read_hi, out);
 }
 
@@ -543,8 +607,9 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint32_t *t
   const TileRange tr = enum_tile(a, t);
   const TileSrc ts = stage_tile(a, tr, L);
   K keys[STREAM_KPT];
-  const int n = enum_keys<K, STREAM_KPT>(a, ts, tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
-                                         tr.end, tr.read_lo, tr.read_hi, keys);
+  const int n = enum_keys<K, STREAM_KPT, true>(a, ts,
+                                               tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
+                                               tr.end, tr.read_lo, tr.read_hi, keys);
 #pragma unroll
   for (int r = 0; r < STREAM_KPT; ++r)
     if (r < n && (!SL || in_slice(a, keys[r]))) atomicAdd(&h[msd_digit(keys[r], a.bits, 0)], 1u);
@@ -582,8 +647,9 @@ __global__ __launch_bounds__(STREAM_NT) void k_prefix_hist(EnumArgs a, uint64_t 
     const TileRange tr = enum_tile(a, t);
     const TileSrc ts = stage_tile(a, tr, L);
     K keys[STREAM_KPT];
-    const int n = enum_keys<K, STREAM_KPT>(a, ts, tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
-                                           tr.end, tr.read_lo, tr.read_hi, keys);
+    const int n = enum_keys<K, STREAM_KPT, true>(a, ts,
+                                                 tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
+                                                 tr.end, tr.read_lo, tr.read_hi, keys);
 #pragma unroll
     for (int r = 0; r < STREAM_KPT; ++r)
       if (r < n) atomicAdd(&h[key_prefix_bits(keys[r], a.bits)], 1u);
