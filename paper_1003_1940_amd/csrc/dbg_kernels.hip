@@ -522,75 +522,125 @@ __device__ __forceinline__ int enum_keys_global(const EnumArgs &a, const TileSrc
   return n;
 }
 
-// The staged enumeration without divergence: a thread's KPT consecutive keys
-// meet at most one read start when reads hold at least KPT keys, so every thread
-// computes both seeds up front (its first key's, and the first key's of the read
-// that starts inside its range, if any) and then only rolls, taking the second
-// seed with a select at the step where that read starts.  Returns -1, having
-// written nothing, when some thread of the wave meets two read starts (short
-// reads): the wave then takes enum_keys_staged.
-template <typename K, int KPT>
-__device__ __forceinline__ int enum_keys_two_seeds(const EnumArgs &a, const TileSrc &ts,
-                                                   uint64_t g0, uint64_t g_end, K (&out)[KPT]) {
+// Where a thread's KPT positions start in the staged stream: P for the first
+// and, when a read starts inside them, that read's first base P2 and the step rs
+// at which it starts (otherwise P2 = P and rs = KPT).  A thread's positions meet
+// at most one read start when reads hold at least KPT keys; `two` is set when
+// some position meets a second one.
+struct Seeds {
+  uint32_t gl0, glast;  // the thread's first position and its range end (tile-local)
+  uint32_t P, P2, rs;
+  bool two;
+};
+
+template <int KPT>
+__device__ __forceinline__ Seeds find_seeds(const TileSrc &ts, uint64_t g0, uint64_t g_end) {
+  Seeds s;
   const bool any = g0 < g_end;
-  const uint32_t gl0 = any ? (uint32_t)(g0 - ts.g_base) : 0u;
+  s.gl0 = any ? (uint32_t)(g0 - ts.g_base) : 0u;
   const uint32_t gle = any ? (uint32_t)(g_end - ts.g_base) : 0u;
-  const uint32_t glast = gl0 + (uint32_t)KPT < gle ? gl0 + (uint32_t)KPT : gle;  // range end
+  s.glast = s.gl0 + (uint32_t)KPT < gle ? s.gl0 + (uint32_t)KPT : gle;
   uint32_t lo = 0, hi = ts.nr - 1;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (ts.lrb[mid] <= gl0) lo = mid;
+    if (ts.lrb[mid] <= s.gl0) lo = mid;
     else hi = mid;
   }
   const uint32_t next = ts.lrb[lo + 1];  // first key of the following read (> gl0)
-  const bool sw = any && next < glast;
+  const bool sw = any && next < s.glast;
   uint32_t j = lo + 1;
   if (sw)
     while (ts.lrb[j + 1] == next) ++j;  // past reads with no key
-  const bool two = sw && ts.lrb[j + 1] < glast;
-  if (__any(two)) return -1;
+  s.two = sw && ts.lrb[j + 1] < s.glast;
+  s.P = ts.loff[lo] + (s.gl0 - ts.lrb[lo]);
+  s.P2 = sw ? ts.loff[j] : s.P;
+  s.rs = sw ? next - s.gl0 : (uint32_t)KPT;
+  return s;
+}
+
+// The 32 bases of the staged stream from base S, first base in the top bits.
+__device__ __forceinline__ uint64_t window32(lds_u64 *w, uint32_t S) {
+  const uint32_t wi = S >> 5;
+  const int o = (int)(S & 31) * 2;
+  const uint64_t w0 = w[wi], w1 = w[wi + 1];
+  return o ? ((w0 << o) | (w1 >> (64 - o))) : w0;
+}
+
+// Heads of the canonical keys: the first H = min(6, len) bases of the canonical
+// key at each of a thread's positions, as a 2H-bit integer, which fixes the key's
+// first radix digit and its slice prefix.  Taking the first bases of an integer
+// key is monotone, so the head of the smaller of the key and its reverse
+// complement (Sec. 2) is the smaller of their heads: the forward k-mer's first H
+// bases and the reverse complement of its last H bases.  Both come, for all 16
+// positions of a seed, from one 32-base window each (16 positions + H - 1 <= 21
+// bases), with 32-bit field extracts: no key-wide arithmetic.  A seed that starts
+// at step rs is read from its virtual start P2 - rs (at or after the previous
+// read's last k-mer base), so that step r of either seed sits at the same window
+// offset.  Same read-start rules and return value as enum_keys_two_seeds.
+struct HeadWin {
+  uint32_t f0, f1;  // forward bases [S, S + 16) and [S + 8, S + 24)
+  uint32_t r0, r1;  // reverse complement of the last-H windows, steps 0..7 and 8..15
+};
+
+__device__ __forceinline__ HeadWin head_windows(lds_u64 *w, uint32_t S, int len, int H) {
+  HeadWin hw;
+  const uint64_t f = window32(w, S);
+  hw.f0 = (uint32_t)(f >> 32);
+  hw.f1 = (uint32_t)(f >> 16);
+  // complement base S + len - H + j lands in bits [2j, 2j + 2)
+  const uint64_t rc = reverse_pairs64(~window32(w, S + (uint32_t)(len - H)));
+  hw.r0 = (uint32_t)rc;
+  hw.r1 = (uint32_t)(rc >> 16);
+  return hw;
+}
+
+__device__ __forceinline__ uint32_t head_at(const HeadWin &hw, int r, int H) {
+  const uint32_t width = 2u * (uint32_t)H;
+  const uint32_t fw = r < 8 ? __builtin_amdgcn_ubfe(hw.f0, 32u - width - 2u * r, width)
+                            : __builtin_amdgcn_ubfe(hw.f1, 32u - width - 2u * (r - 8), width);
+  const uint32_t rc = r < 8 ? __builtin_amdgcn_ubfe(hw.r0, 2u * r, width)
+                            : __builtin_amdgcn_ubfe(hw.r1, 2u * (r - 8), width);
+  return rc < fw ? rc : fw;
+}
+
+template <int KPT>
+__device__ __forceinline__ int enum_heads_two_seeds(const EnumArgs &a, const TileSrc &ts,
+                                                    uint64_t g0, uint64_t g_end,
+                                                    uint32_t (&out)[KPT]) {
+  static_assert(KPT == 16, "the head windows cover 16 positions");
+  const Seeds sd = find_seeds<KPT>(ts, g0, g_end);
+  if (__any(sd.two)) return -1;
   const int len = a.len;
-  const K mask = low_mask<K>(2 * len);
-  const int top = 2 * len - 2;
-  uint32_t P = ts.loff[lo] + (gl0 - ts.lrb[lo]);
-  const uint32_t P2 = sw ? ts.loff[j] : P;
-  const uint32_t rs = sw ? next - gl0 : (uint32_t)KPT;  // step that starts the new read
-  K fw = extract_staged(ts.lw, P, len, K());
-  K rc = revcomp(fw, len);
-  const K fw2 = extract_staged(ts.lw, P2, len, K());
-  const K rc2 = revcomp(fw2, len);
+  const int H = len < 6 ? len : 6;
+  const HeadWin w1 = head_windows(ts.lw, sd.P, len, H);
+  const HeadWin w2 = head_windows(ts.lw, sd.rs < (uint32_t)KPT ? sd.P2 - sd.rs : sd.P, len, H);
   int n = 0;
 #pragma unroll
   for (int r = 0; r < KPT; ++r) {
-    if (r > 0) {
-      const uint32_t q = P + (uint32_t)len;
-      const uint32_t c = (uint32_t)(ts.lw[q >> 5] >> (62 - 2 * (int)(q & 31))) & 3u;
-      const bool now = (uint32_t)r == rs;
-      fw = now ? fw2 : (((fw << 2) | (K)c) & mask);
-      rc = now ? rc2 : ((rc >> 2) | ((K)(3u - c) << top));
-      P = now ? P2 : P + 1;
-    }
-    if (gl0 + (uint32_t)r < glast) {
-      out[r] = rc < fw ? rc : fw;
+    const uint32_t h1 = head_at(w1, r, H), h2 = head_at(w2, r, H);
+    if (sd.gl0 + (uint32_t)r < sd.glast) {
+      out[r] = (uint32_t)r < sd.rs ? h1 : h2;
       ++n;
     }
   }
   return n;
 }
 
-// TWO: try the two-seed form first (the histogram pass; in the scatter pass its
-// extra registers cost more occupancy than its divergence saves: measured).
-template <typename K, int KPT, bool TWO = false>
+// The first radix digit and the slice prefix of a key from its head (the first
+// H = min(6, len) bases): the same values as msd_digit(key, 2 len, 0) and
+// key_prefix_bits(key, 2 len).
+__device__ __forceinline__ uint32_t head_digit(uint32_t head, int len) {
+  return len >= 4 ? head >> (2 * (len < 6 ? len : 6) - 8) : head;
+}
+__device__ __forceinline__ uint32_t head_prefix(uint32_t head, int len) {
+  return head << (PFX_BITS - 2 * (len < 6 ? len : 6));
+}
+
+template <typename K, int KPT>
 __device__ __forceinline__ int enum_keys(const EnumArgs &a, const TileSrc &ts, uint64_t g0,
                                          uint64_t g_end, uint64_t read_lo, uint64_t read_hi,
                                          K (&out)[KPT]) {
-  if (ts.fast) {
-    if constexpr (TWO) {
-      const int n = enum_keys_two_seeds<K, KPT>(a, ts, g0, g_end, out);
-      if (n >= 0) return n;
-    }
-    return enum_keys_staged<K, KPT>(a, ts, g0, g_end, out);
-  }
+  if (ts.fast) return enum_keys_staged<K, KPT>(a, ts, g0, g_end, out);
   return enum_keys_global<K, KPT>(a, ts, g0, g_end, read_lo, read_hi, out);
 }
 
@@ -606,13 +656,24 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint32_t *t
   h[threadIdx.x] = 0;
   const TileRange tr = enum_tile(a, t);
   const TileSrc ts = stage_tile(a, tr, L);
-  K keys[STREAM_KPT];
-  const int n = enum_keys<K, STREAM_KPT, true>(a, ts,
-                                               tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
-                                               tr.end, tr.read_lo, tr.read_hi, keys);
+  const uint64_t g0 = tr.start + threadIdx.x * (uint64_t)STREAM_KPT;
+  uint32_t heads[STREAM_KPT];
+  const int nh = ts.fast ? enum_heads_two_seeds<STREAM_KPT>(a, ts, g0, tr.end, heads) : -1;
+  if (nh >= 0) {
 #pragma unroll
-  for (int r = 0; r < STREAM_KPT; ++r)
-    if (r < n && (!SL || in_slice(a, keys[r]))) atomicAdd(&h[msd_digit(keys[r], a.bits, 0)], 1u);
+    for (int r = 0; r < STREAM_KPT; ++r) {
+      const uint32_t p = head_prefix(heads[r], a.len);
+      if (r < nh && (!SL || (p >= a.pfx_lo && p < a.pfx_hi)))
+        atomicAdd(&h[head_digit(heads[r], a.len)], 1u);
+    }
+  } else {
+    K keys[STREAM_KPT];
+    const int n = enum_keys<K, STREAM_KPT>(a, ts, g0, tr.end, tr.read_lo, tr.read_hi, keys);
+#pragma unroll
+    for (int r = 0; r < STREAM_KPT; ++r)
+      if (r < n && (!SL || in_slice(a, keys[r])))
+        atomicAdd(&h[msd_digit(keys[r], a.bits, 0)], 1u);
+  }
   __syncthreads();
   thist[t * 256 + threadIdx.x] = h[threadIdx.x];
 }
@@ -646,13 +707,20 @@ __global__ __launch_bounds__(STREAM_NT) void k_prefix_hist(EnumArgs a, uint64_t 
     __syncthreads();  // the previous tile's staged words are dead
     const TileRange tr = enum_tile(a, t);
     const TileSrc ts = stage_tile(a, tr, L);
-    K keys[STREAM_KPT];
-    const int n = enum_keys<K, STREAM_KPT, true>(a, ts,
-                                                 tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
-                                                 tr.end, tr.read_lo, tr.read_hi, keys);
+    const uint64_t g0 = tr.start + threadIdx.x * (uint64_t)STREAM_KPT;
+    uint32_t heads[STREAM_KPT];
+    const int nh = ts.fast ? enum_heads_two_seeds<STREAM_KPT>(a, ts, g0, tr.end, heads) : -1;
+    if (nh >= 0) {
 #pragma unroll
-    for (int r = 0; r < STREAM_KPT; ++r)
-      if (r < n) atomicAdd(&h[key_prefix_bits(keys[r], a.bits)], 1u);
+      for (int r = 0; r < STREAM_KPT; ++r)
+        if (r < nh) atomicAdd(&h[head_prefix(heads[r], a.len)], 1u);
+    } else {
+      K keys[STREAM_KPT];
+      const int n = enum_keys<K, STREAM_KPT>(a, ts, g0, tr.end, tr.read_lo, tr.read_hi, keys);
+#pragma unroll
+      for (int r = 0; r < STREAM_KPT; ++r)
+        if (r < n) atomicAdd(&h[key_prefix_bits(keys[r], a.bits)], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < PFX_BINS; i += STREAM_NT)
