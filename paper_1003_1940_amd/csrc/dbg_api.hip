@@ -78,8 +78,7 @@ Layout make_layout(uint64_t n_reads, uint64_t n_sets, uint64_t max_keys, int k,
   L.block_sums = take(L.read_blocks * sizeof(uint64_t));
   L.set_kbase = take((n_sets + 1) * sizeof(uint64_t));
   L.set_tbase = take((n_sets + 1) * sizeof(uint64_t));
-  L.tile_read = take(L.max_tiles * sizeof(uint64_t));
-  L.tile_set = take(L.max_tiles * sizeof(uint32_t));
+  L.tiles = take(L.max_tiles * sizeof(TileDesc));
   // per-tile digit counts: enumeration tiles, or the tiles of a partition level
   // (at most one partial tile per bucket more)
   const uint64_t rows = L.max_tiles + L.item_cap;

@@ -92,6 +92,18 @@ struct SegBatch {  // digits [da, db) of an in-tile bucket: one segment per tile
 // Beside every SegBatch, a table of SEG_TILES words: word i = the range's
 // first and end offsets inside tile i (each at most TILE, 16 bits apiece).
 
+// One enumeration tile: everything its workgroup needs before loading the packed
+// words, in one 64-byte record (so a tile's set-up is one dependent load).
+struct TileDesc {
+  uint64_t start;             // its first key (key index over all positions)
+  uint64_t read_lo, read_hi;  // reads [read_lo, read_hi) hold its keys
+  uint64_t g_base;            // first key of read read_lo
+  uint64_t wb, we;            // packed words [wb, we) hold those reads' bases
+  uint64_t t_first;           // first tile of its read set
+  uint32_t set;               // its read set
+  uint32_t n;                 // its keys (at most TILE)
+};
+
 struct Batch {  // consecutive small buckets [off, off + size) of buffer `src`
   uint64_t off;
   uint32_t size;
@@ -113,7 +125,7 @@ __host__ __device__ inline uint32_t batch_db(uint32_t src) { return (src >> 14) 
 
 // Byte layout of a caller-provided workspace.
 struct Layout {
-  size_t ctl, set_read_off, rbase, block_sums, set_kbase, set_tbase, tile_read, tile_set;
+  size_t ctl, set_read_off, rbase, block_sums, set_kbase, set_tbase, tiles;
   size_t thist, csum, cursor0, items[2], hist[2], cursor, batches, uniform, rle_heads, bits, set_uoff;
   size_t counts;  // uint32 count of each distinct key, beside buffer 0
   size_t segb;    // SegBatch list of the in-tile level

@@ -254,10 +254,13 @@ __global__ __launch_bounds__(1024) void k_set_setup(const uint64_t *rbase, uint6
   if (threadIdx.x == 0) ctl->n_tiles = carry;
 }
 
-// Tile -> (set, read whose key range contains the tile's first key).
-__global__ void k_tile_map(const uint64_t *rbase, const uint64_t *set_read_off, uint64_t n_sets,
-                           const uint64_t *set_kbase, const uint64_t *set_tbase,
-                           uint64_t *tile_read, uint32_t *tile_set, uint64_t max_tiles, Ctl *ctl) {
+// Tile -> its descriptor: the set, the keys, the reads holding them (the read
+// whose key range contains the tile's first key, through the one holding its
+// last) and the packed words holding those reads.
+__global__ void k_tile_map(const uint64_t *rbase, const uint64_t *offsets,
+                           const uint64_t *set_read_off, uint64_t n_sets,
+                           const uint64_t *set_kbase, const uint64_t *set_tbase, TileDesc *tiles,
+                           uint64_t max_tiles, Ctl *ctl) {
   const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (ctl->status || t >= ctl->n_tiles) return;
   if (t >= max_tiles) {
@@ -265,10 +268,25 @@ __global__ void k_tile_map(const uint64_t *rbase, const uint64_t *set_read_off, 
     return;
   }
   const uint64_t s = upper_bound(set_tbase, 0, n_sets + 1, t) - 1;
-  const uint64_t g = set_kbase[s] + (t - set_tbase[s]) * TILE;
+  const uint64_t tb = set_tbase[s];
+  const uint64_t g = set_kbase[s] + (t - tb) * TILE;
+  const uint64_t se = set_kbase[s + 1];
+  const uint64_t ge = g + TILE < se ? g + TILE : se;
   const uint64_t r0 = set_read_off[s], r1 = set_read_off[s + 1];
-  tile_read[t] = upper_bound(rbase, r0, r1 + 1, g) - 1;
-  tile_set[t] = (uint32_t)s;
+  const uint64_t lo = upper_bound(rbase, r0, r1 + 1, g) - 1;
+  // one past the read holding the next tile's first key, or the set's end
+  const uint64_t hi = t + 1 < set_tbase[s + 1] ? upper_bound(rbase, r0, r1 + 1, ge) : r1;
+  TileDesc d;
+  d.start = g;
+  d.read_lo = lo;
+  d.read_hi = hi;
+  d.g_base = rbase[lo];
+  d.wb = offsets[lo] >> 5;
+  d.we = (offsets[hi] + 31) >> 5;
+  d.t_first = tb;
+  d.set = (uint32_t)s;
+  d.n = (uint32_t)(ge - g);
+  tiles[t] = d;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,11 +297,7 @@ struct EnumArgs {
   uint64_t n_words;
   const uint64_t *offsets;
   const uint64_t *rbase;
-  const uint64_t *set_read_off;
-  const uint64_t *set_kbase;
-  const uint64_t *set_tbase;
-  const uint64_t *tile_read;
-  const uint32_t *tile_set;
+  const TileDesc *tiles;
   int len;   // bases per key
   int bits;  // 2 * len
   int gate;
@@ -303,18 +317,22 @@ template <typename K> __device__ __forceinline__ bool in_slice(const EnumArgs &a
 
 struct TileRange {
   uint64_t start, end, read_lo, read_hi;
+  uint64_t g_base, wb, we, t_first;
   uint32_t set;
 };
 
 __device__ __forceinline__ TileRange enum_tile(const EnumArgs &a, uint64_t t) {
+  const TileDesc d = a.tiles[t];
   TileRange r;
-  const uint32_t s = a.tile_set[t];
-  r.set = s;
-  r.start = a.set_kbase[s] + (t - a.set_tbase[s]) * TILE;
-  const uint64_t se = a.set_kbase[s + 1];
-  r.end = r.start + TILE < se ? r.start + TILE : se;
-  r.read_lo = a.tile_read[t];
-  r.read_hi = (t + 1 < a.set_tbase[s + 1]) ? a.tile_read[t + 1] + 1 : a.set_read_off[s + 1];
+  r.start = d.start;
+  r.end = d.start + d.n;
+  r.read_lo = d.read_lo;
+  r.read_hi = d.read_hi;
+  r.g_base = d.g_base;
+  r.wb = d.wb;
+  r.we = d.we;
+  r.t_first = d.t_first;
+  r.set = d.set;
   return r;
 }
 
@@ -364,13 +382,12 @@ __device__ __forceinline__ TileSrc stage_tile(const EnumArgs &a, const TileRange
   ts.lw = (lds_u64 *)L.words;
   ts.lrb = (lds_u32 *)L.rb;
   ts.loff = (lds_u32 *)L.off;
-  const uint64_t wb = a.offsets[tr.read_lo] >> 5;
-  const uint64_t we = (a.offsets[tr.read_hi] + 31) >> 5;
-  const uint64_t nw = we - wb + 2;
+  const uint64_t wb = tr.wb;
+  const uint64_t nw = tr.we - wb + 2;
   const uint64_t nr = tr.read_hi - tr.read_lo + 1;
   ts.fast = nw <= ENUM_WCAP + 2 && nr <= ENUM_RCAP;
   ts.nr = (uint32_t)nr;
-  ts.g_base = a.rbase[tr.read_lo];
+  ts.g_base = tr.g_base;
   if (ts.fast) {
     for (uint32_t i = threadIdx.x; i < (uint32_t)nw; i += blockDim.x)
       L.words[i] = wb + i < a.n_words ? a.packed[wb + i] : 0ull;
@@ -944,16 +961,16 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_scatter(EnumArgs a, const ui
   const uint64_t t = xcd_tile(blockIdx.x, nt);
   if (t >= nt) return;
   const TileRange tr = enum_tile(a, t);
+  // digit d's destination (loaded before the staging, whose barrier would hold
+  // the loads back): tile prefixes are counted modulo 2^32; a difference is exact
+  // because a table holds fewer than 2^32 keys
+  const uint32_t d = threadIdx.x;
+  const uint64_t base = cursor0[(uint64_t)tr.set * 256 + d] +
+                        (uint32_t)(tpre[t * 256 + d] - tpre[tr.t_first * 256 + d]);
   const TileSrc ts = stage_tile(a, tr, s.stage);
   K keys[STREAM_KPT];
   const int n = enum_keys<K, STREAM_KPT>(a, ts, tr.start + threadIdx.x * (uint64_t)STREAM_KPT,
                                          tr.end, tr.read_lo, tr.read_hi, keys);
-  const uint64_t t_first = a.set_tbase[tr.set];
-  const uint32_t d = threadIdx.x;
-  // tile prefixes are counted modulo 2^32; a difference is exact because a table
-  // holds fewer than 2^32 keys
-  const uint64_t base = cursor0[(uint64_t)tr.set * 256 + d] +
-                        (uint32_t)(tpre[t * 256 + d] - tpre[t_first * 256 + d]);
   const uint32_t nowt[STREAM_KPT] = {};
   uint32_t valid = 0xffffffffu;
   if (SL) {
@@ -2728,8 +2745,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   uint64_t *block_sums = reinterpret_cast<uint64_t *>(ws + L.block_sums);
   uint64_t *set_kbase = reinterpret_cast<uint64_t *>(ws + L.set_kbase);
   uint64_t *set_tbase = reinterpret_cast<uint64_t *>(ws + L.set_tbase);
-  uint64_t *tile_read = reinterpret_cast<uint64_t *>(ws + L.tile_read);
-  uint32_t *tile_set = reinterpret_cast<uint32_t *>(ws + L.tile_set);
+  TileDesc *tiles = reinterpret_cast<TileDesc *>(ws + L.tiles);
   uint32_t *thist = reinterpret_cast<uint32_t *>(ws + L.thist);
   uint32_t *csum = reinterpret_cast<uint32_t *>(ws + L.csum);
   uint64_t *cursor0 = reinterpret_cast<uint64_t *>(ws + L.cursor0);
@@ -2777,7 +2793,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   hipLaunchKernelGGL(k_set_setup, dim3(1), dim3(1024), 0, st, rbase, A.n_reads, set_read_off, S,
                      A.max_positions, set_kbase, set_tbase, ctl);
   hipLaunchKernelGGL(k_tile_map, dim3(grid_for(L.max_tiles, 256, 1u << 30)), dim3(256), 0, st,
-                     rbase, set_read_off, S, set_kbase, set_tbase, tile_read, tile_set,
+                     rbase, A.read_offsets, set_read_off, S, set_kbase, set_tbase, tiles,
                      L.max_tiles, ctl);
   if (two_routes)
     hipLaunchKernelGGL(k_node_path, dim3(1), dim3(1), 0, st, ctl, A.n_reads, S,
@@ -2785,8 +2801,8 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                        (uint64_t)(A.max_keys + 2) * (uint64_t)L.key_bytes, (uint64_t)L.weights,
                        L.key_bytes);
   stage(ev + 1, st);
-  EnumArgs ea{A.packed, n_words, A.read_offsets, rbase, set_read_off, set_kbase,
-              set_tbase, tile_read, tile_set, len, bits, g0, A.pfx_lo, A.pfx_hi};
+  EnumArgs ea{A.packed, n_words, A.read_offsets, rbase, tiles, len, bits, g0, A.pfx_lo,
+              A.pfx_hi};
   if (sliced)
     hipLaunchKernelGGL((k_enum_hist<K, true>), dim3((unsigned)L.max_tiles), dim3(STREAM_NT), 0, st,
                        ea, thist, ctl);
@@ -3020,8 +3036,7 @@ static hipError_t run_prefix(const BuildArgs &A, const Layout &L, int len, uint6
   uint64_t *block_sums = reinterpret_cast<uint64_t *>(ws + L.block_sums);
   uint64_t *set_kbase = reinterpret_cast<uint64_t *>(ws + L.set_kbase);
   uint64_t *set_tbase = reinterpret_cast<uint64_t *>(ws + L.set_tbase);
-  uint64_t *tile_read = reinterpret_cast<uint64_t *>(ws + L.tile_read);
-  uint32_t *tile_set = reinterpret_cast<uint32_t *>(ws + L.tile_set);
+  TileDesc *tiles = reinterpret_cast<TileDesc *>(ws + L.tiles);
   hipStream_t st = A.stream;
   hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(1), 0, st, ctl);
   hipLaunchKernelGGL(k_read_reduce, dim3((unsigned)L.read_blocks), dim3(SCAN_NT), 0, st,
@@ -3033,11 +3048,11 @@ static hipError_t run_prefix(const BuildArgs &A, const Layout &L, int len, uint6
   hipLaunchKernelGGL(k_set_setup, dim3(1), dim3(1024), 0, st, rbase, A.n_reads, set_read_off,
                      (uint64_t)1, A.max_positions, set_kbase, set_tbase, ctl);
   hipLaunchKernelGGL(k_tile_map, dim3(grid_for(L.max_tiles, 256, 1u << 30)), dim3(256), 0, st,
-                     rbase, set_read_off, (uint64_t)1, set_kbase, set_tbase, tile_read, tile_set,
-                     L.max_tiles, ctl);
+                     rbase, A.read_offsets, set_read_off, (uint64_t)1, set_kbase, set_tbase,
+                     tiles, L.max_tiles, ctl);
   hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, st, counts, (uint64_t)PFX_BINS, 0ull);
-  EnumArgs ea{A.packed, (A.n_bases + 31) / 32, A.read_offsets, rbase, set_read_off, set_kbase,
-              set_tbase, tile_read, tile_set, len, 2 * len, -1, 0u, PFX_BINS};
+  EnumArgs ea{A.packed, (A.n_bases + 31) / 32, A.read_offsets, rbase, tiles, len, 2 * len, -1,
+              0u, PFX_BINS};
   hipLaunchKernelGGL(k_prefix_hist<K>, dim3(grid_for(L.max_tiles, 1, 2048)), dim3(STREAM_NT), 0,
                      st, ea, counts, ctl);
   return hipGetLastError();

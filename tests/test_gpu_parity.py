@@ -54,7 +54,7 @@ def test_random_small_sets():
         compare_with_oracle(b, o, k, label=f"random[{t}]")
 
 
-@pytest.mark.parametrize("k", [1, 3, 15, 21, 31, 33, 47, 61, 63])
+@pytest.mark.parametrize("k", [1, 3, 5, 7, 15, 21, 31, 33, 47, 61, 63])
 def test_k_sweep(k):
     rng = np.random.default_rng(100 + k)
     g = synth.random_genome(rng, 20_000)

@@ -68,6 +68,16 @@ def test_prefix_counts_match_the_strings():
                                       max(sliced.positions(o, k), 1))
         assert np.array_equal(ec, prefix_ref(b, o, k + 1)), f"edge prefixes k={k}"
         assert np.array_equal(nc, prefix_ref(b, o, k)), f"node prefixes k={k}"
+    # long reads: keys shorter than the 12-bit prefix and than a 4-base digit
+    rng = np.random.default_rng(64)
+    g = synth.random_genome(rng, 5000)
+    rs = synth.sample_reads(rng, g, 400, 150, 0.01)
+    for k in (1, 3, 5, 7):
+        say(f"[gpu-sliced] prefix counts k={k} long reads")
+        packed, offs, n_bases = api.upload(rs.bases, rs.offsets)
+        ec, nc = sliced.prefix_counts(packed, n_bases, offs, k, sliced.positions(rs.offsets, k))
+        assert np.array_equal(ec, prefix_ref(rs.bases, rs.offsets, k + 1)), f"edges k={k}"
+        assert np.array_equal(nc, prefix_ref(rs.bases, rs.offsets, k)), f"nodes k={k}"
     rs = synth.plain_small(scale=0.2)
     packed, offs, n_bases = api.upload(rs.bases, rs.offsets)
     ec, nc = sliced.prefix_counts(packed, n_bases, offs, 31,
