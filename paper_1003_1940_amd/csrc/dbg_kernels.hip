@@ -2546,10 +2546,11 @@ struct OutArgs {
   int k;
 };
 
-// One thread per output row: row i of a tile is the i-th marked position, found
-// from the tile's 128 word popcount prefixes (kept in LDS) by a binary search
-// and a bit select, so consecutive threads read consecutive distinct keys and
-// write consecutive rows with no staging of the keys themselves.
+// One thread per output row: row i of a tile is the i-th marked position.  The
+// tile's marked positions are first listed in LDS in order (each thread lists the
+// marked bits of one half bitmap word, at its half-word popcount prefix), so
+// consecutive threads read consecutive distinct keys and write consecutive rows
+// with no staging of the keys themselves.
 constexpr int EMIT_WNT = 256;
 
 template <typename K, bool EDGES>
@@ -2557,8 +2558,8 @@ __global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
                                                          const uint64_t *tile_base, const K *b0,
                                                          const uint32_t *cnts, OutArgs o,
                                                          uint64_t n_tiles, const Ctl *ctl) {
-  __shared__ uint32_t wpre[EMIT_NT + 1];  // marked positions before each word of the tile
-  __shared__ uint32_t wbits[EMIT_NT];
+  static_assert(EMIT_WNT == 2 * EMIT_NT, "one thread per half bitmap word");
+  __shared__ uint16_t lpos[TILE];  // marked positions of the tile, in order
   __shared__ uint64_t wsum[EMIT_WNT / 64 + 1];
   if (ctl->status) return;
   // tiles holding key positions (the endpoint records of a node table, or the
@@ -2568,26 +2569,20 @@ __global__ __launch_bounds__(EMIT_WNT) void k_emit_write(const uint32_t *bits,
   const uint64_t tile = xcd_tile(blockIdx.x, nt_used);
   if (tile >= nt_used) return;
   const uint64_t w0 = tile * (uint64_t)EMIT_NT;
-  const uint32_t word = threadIdx.x < (uint32_t)EMIT_NT ? bits[w0 + threadIdx.x] : 0u;
+  const uint32_t word = bits[w0 + (threadIdx.x >> 1)];
+  // bit b of word w marks position 32 w + b: even threads take bits 0..15
+  uint32_t half = (threadIdx.x & 1) ? word >> 16 : word & 0xffffu;
   uint64_t tot;
-  const uint32_t ex = (uint32_t)block_exclusive_scan<EMIT_WNT>((uint64_t)__popc(word), wsum, &tot);
-  if (threadIdx.x < (uint32_t)EMIT_NT) {
-    wpre[threadIdx.x] = ex;
-    wbits[threadIdx.x] = word;
+  uint32_t e = (uint32_t)block_exclusive_scan<EMIT_WNT>((uint64_t)__popc(half), wsum, &tot);
+  const uint32_t p0 = threadIdx.x * 16u;
+  while (half) {
+    lpos[e++] = (uint16_t)(p0 + (uint32_t)(__ffs(half) - 1));
+    half &= half - 1u;
   }
-  if (threadIdx.x == 0) wpre[EMIT_NT] = (uint32_t)tot;
   __syncthreads();
   const uint64_t base = tile_base[tile];
   for (uint32_t i = threadIdx.x; i < (uint32_t)tot; i += EMIT_WNT) {
-    uint32_t lo = 0, hi = EMIT_NT;  // the last word w with wpre[w] <= i
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (wpre[mid] <= i) lo = mid;
-      else hi = mid;
-    }
-    uint32_t wd = wbits[lo];
-    for (uint32_t r = i - wpre[lo]; r; --r) wd &= wd - 1;  // drop the lower marked bits
-    const uint64_t pos = ((w0 + lo) << 5) + (uint64_t)(__ffs(wd) - 1);
+    const uint64_t pos = (w0 << 5) + lpos[i];
     const uint64_t j = base + i;
     if (j >= o.capacity) break;
     const K key = b0[pos];
