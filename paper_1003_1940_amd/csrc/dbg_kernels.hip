@@ -114,25 +114,53 @@ __device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t n) {
 constexpr int SCAN_NT = 256, SCAN_PT = 16;
 constexpr uint64_t SCAN_TILE = (uint64_t)SCAN_NT * SCAN_PT;
 
-__device__ __forceinline__ uint64_t read_key_count(const uint64_t *off, uint64_t i, int len,
-                                                   Ctl *ctl) {
-  const uint64_t a = off[i], b = off[i + 1];
-  if (b < a) {
-    set_status(ctl, DBG_E_OFFSETS);
-    return 0;
+// A workgroup's SCAN_TILE reads: their offsets (and the next one) are loaded with
+// consecutive threads on consecutive words into LDS, where thread t takes reads
+// SCAN_PT t .. SCAN_PT t + SCAN_PT - 1.  One padding word after every SCAN_PT
+// keeps those per-thread runs in different banks.
+__device__ __forceinline__ uint32_t scan_pad(uint32_t i) { return i + i / SCAN_PT; }
+constexpr uint32_t SCAN_LDS = SCAN_TILE + SCAN_TILE / SCAN_PT + 2;
+
+__device__ __forceinline__ void stage_offsets(const uint64_t *off, uint64_t n_reads, uint64_t b0,
+                                              uint64_t *lo) {
+  for (uint32_t i = threadIdx.x; i <= (uint32_t)SCAN_TILE; i += SCAN_NT)
+    lo[scan_pad(i)] = b0 + i <= n_reads ? off[b0 + i] : 0;
+  __syncthreads();
+}
+
+// Key counts of this thread's reads (0 past the last read); a decreasing offset
+// is reported.
+__device__ __forceinline__ void read_key_counts(const uint64_t *lo, uint64_t b0,
+                                                uint64_t n_reads, int len,
+                                                uint64_t (&c)[SCAN_PT], Ctl *ctl) {
+  const uint32_t i0 = threadIdx.x * SCAN_PT;
+  uint64_t a = lo[scan_pad(i0)];
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < SCAN_PT; ++r) {
+    const uint64_t b = lo[scan_pad(i0 + r + 1)];
+    c[r] = 0;
+    if (b0 + i0 + r < n_reads) {
+      bad |= b < a;
+      const uint64_t L = b - a;
+      c[r] = b >= a && L + 1 > (uint64_t)len ? L + 1 - (uint64_t)len : 0;
+    }
+    a = b;
   }
-  const uint64_t L = b - a;
-  return L + 1 > (uint64_t)len ? L + 1 - (uint64_t)len : 0;
+  if (bad) set_status(ctl, DBG_E_OFFSETS);
 }
 
 __global__ __launch_bounds__(SCAN_NT) void k_read_reduce(const uint64_t *off, uint64_t n_reads,
                                                          uint64_t n_bases, int len,
                                                          uint64_t *block_sums, Ctl *ctl) {
   __shared__ uint64_t wsum[SCAN_NT / 64 + 1];
-  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + threadIdx.x * (uint64_t)SCAN_PT;
-  uint64_t s = 0;
-  for (int r = 0; r < SCAN_PT; ++r)
-    if (base + r < n_reads) s += read_key_count(off, base + r, len, ctl);
+  __shared__ uint64_t lo[SCAN_LDS];
+  const uint64_t b0 = (uint64_t)blockIdx.x * SCAN_TILE;
+  stage_offsets(off, n_reads, b0, lo);
+  uint64_t c[SCAN_PT], s = 0;
+  read_key_counts(lo, b0, n_reads, len, c, ctl);
+#pragma unroll
+  for (int r = 0; r < SCAN_PT; ++r) s += c[r];
   uint64_t total;
   block_exclusive_scan<SCAN_NT>(s, wsum, &total);
   if (threadIdx.x == 0) {
@@ -204,18 +232,26 @@ __global__ __launch_bounds__(SCAN_NT) void k_read_apply(const uint64_t *off, uin
                                                         int len, const uint64_t *block_sums,
                                                         uint64_t *rbase, Ctl *ctl) {
   __shared__ uint64_t wsum[SCAN_NT / 64 + 1];
-  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + threadIdx.x * (uint64_t)SCAN_PT;
+  __shared__ uint64_t lo[SCAN_LDS];
+  const uint64_t b0 = (uint64_t)blockIdx.x * SCAN_TILE;
+  stage_offsets(off, n_reads, b0, lo);
   uint64_t c[SCAN_PT], s = 0;
-  for (int r = 0; r < SCAN_PT; ++r) {
-    c[r] = base + r < n_reads ? read_key_count(off, base + r, len, ctl) : 0;
-    s += c[r];
-  }
+  read_key_counts(lo, b0, n_reads, len, c, ctl);
+#pragma unroll
+  for (int r = 0; r < SCAN_PT; ++r) s += c[r];
   uint64_t total;
   uint64_t ex = block_exclusive_scan<SCAN_NT>(s, wsum, &total) + block_sums[blockIdx.x];
+  __syncthreads();  // every thread has read its offsets: the prefixes go in their place
+  const uint32_t i0 = threadIdx.x * SCAN_PT;
+#pragma unroll
   for (int r = 0; r < SCAN_PT; ++r) {
-    if (base + r <= n_reads) rbase[base + r] = ex;  // rbase[n_reads] = total keys
+    lo[scan_pad(i0 + (uint32_t)r)] = ex;
     ex += c[r];
   }
+  __syncthreads();
+  // the grid covers reads 0 .. n_reads, so rbase[n_reads] (= total keys) too
+  for (uint32_t i = threadIdx.x; i < (uint32_t)SCAN_TILE; i += SCAN_NT)
+    if (b0 + i <= n_reads) rbase[b0 + i] = lo[scan_pad(i)];
 }
 
 // Per-set key ranges and enumeration tiles.  One workgroup.
@@ -2526,14 +2562,33 @@ __global__ void k_rec_init(Ctl *ctl, Item *items0, uint64_t *hist0) {
 
 constexpr int EMIT_NT = (int)(TILE / 32);
 
-__global__ __launch_bounds__(EMIT_NT) void k_emit_count(const uint32_t *bits, uint64_t *tile_cnt,
-                                                        const Ctl *ctl) {
-  __shared__ uint64_t wsum[EMIT_NT / 64 + 1];
+// Marked positions per tile: a wave counts EMIT_TPW tiles, two bitmap words per
+// lane each, with all their loads in flight at once.
+constexpr int EMIT_TPW = 8;
+constexpr int EMIT_CNT_NT = 256;
+constexpr uint64_t EMIT_CNT_TILES = (uint64_t)EMIT_CNT_NT / 64 * EMIT_TPW;  // per workgroup
+
+__global__ __launch_bounds__(EMIT_CNT_NT) void k_emit_count(const uint32_t *bits,
+                                                            uint64_t *tile_cnt, uint64_t n_tiles,
+                                                            const Ctl *ctl) {
+  static_assert(EMIT_NT == 2 * 64, "two words per lane");
   if (ctl->status) return;
-  const uint32_t c = (uint32_t)__popc(bits[blockIdx.x * (uint64_t)EMIT_NT + threadIdx.x]);
-  uint64_t tot;
-  block_exclusive_scan<EMIT_NT>((uint64_t)c, wsum, &tot);
-  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
+  const uint64_t t0 = (blockIdx.x * (uint64_t)EMIT_CNT_NT + threadIdx.x) / 64 * EMIT_TPW;
+  const uint32_t lane = lane_id();
+  uint32_t c[EMIT_TPW];
+#pragma unroll
+  for (int j = 0; j < EMIT_TPW; ++j) {
+    c[j] = 0;
+    if (t0 + j < n_tiles) {
+      const uint2 w = reinterpret_cast<const uint2 *>(bits + (t0 + j) * EMIT_NT)[lane];
+      c[j] = (uint32_t)(__popc(w.x) + __popc(w.y));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < EMIT_TPW; ++j) {
+    const uint32_t tot = wave_sum(c[j]);
+    if (lane == 0 && t0 + j < n_tiles) tile_cnt[t0 + j] = tot;
+  }
 }
 
 struct OutArgs {
@@ -2965,8 +3020,9 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   if (two_routes)
     hipLaunchKernelGGL(k_uniform_emit_w<K>, dim3(64), dim3(256), 0, st, uniform, &ctl->n_uniform,
                        x0, x1, wt0, wt1, cnts, runbits, ctl, 1);
-  hipLaunchKernelGGL(k_emit_count, dim3((unsigned)L.rle_tiles), dim3(EMIT_NT), 0, st, runbits,
-                     rle_heads, ctl);
+  hipLaunchKernelGGL(k_emit_count,
+                     dim3((unsigned)((L.rle_tiles + EMIT_CNT_TILES - 1) / EMIT_CNT_TILES)),
+                     dim3(EMIT_CNT_NT), 0, st, runbits, rle_heads, L.rle_tiles, ctl);
   {
     const uint64_t nch = (L.rle_tiles + SCAN_TILE - 1) / SCAN_TILE;
     uint64_t *rle_sums = reinterpret_cast<uint64_t *>(ws + L.rle_sums);
