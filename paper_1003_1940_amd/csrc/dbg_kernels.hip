@@ -806,15 +806,16 @@ __global__ __launch_bounds__(256) void k_col_reduce(const uint32_t *thist, uint3
   csum[blockIdx.x * 256 + threadIdx.x] = sum;
 }
 
-// One workgroup of 1024 threads: column d = tid % 256 is scanned in four parts.
-__global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const uint64_t *n_tiles_p,
+// One workgroup per digit d: its column of chunk sums, a contiguous run of chunks
+// per thread (sums modulo 2^32, like the tile prefixes).
+__global__ __launch_bounds__(256) void k_col_scan(uint32_t *csum, const uint64_t *n_tiles_p,
                                                   const Ctl *ctl, int gate) {
-  __shared__ uint32_t part[4][256];
+  __shared__ uint64_t wsum[256 / 64 + 1];
   if (ctl->status || gated_off(ctl, gate)) return;
   const uint64_t nc = (*n_tiles_p + COL_CHUNK - 1) / COL_CHUNK;
-  const uint32_t d = threadIdx.x & 255, pi = threadIdx.x >> 8;
-  const uint64_t q = (nc + 3) / 4;
-  const uint64_t c0 = pi * q, c1 = c0 + q < nc ? c0 + q : nc;
+  const uint32_t d = blockIdx.x;
+  const uint64_t q = (nc + 255) / 256;
+  const uint64_t c0 = threadIdx.x * q, c1 = c0 + q < nc ? c0 + q : nc;
   uint32_t sum = 0;
   for (uint64_t c = c0; c < c1; c += COL_BATCH) {
     uint32_t v[COL_BATCH];
@@ -823,10 +824,8 @@ __global__ __launch_bounds__(1024) void k_col_scan(uint32_t *csum, const uint64_
 #pragma unroll
     for (int i = 0; i < COL_BATCH; ++i) sum += v[i];
   }
-  part[pi][d] = sum;
-  __syncthreads();
-  uint32_t run = 0;
-  for (uint32_t i = 0; i < pi; ++i) run += part[i][d];
+  uint64_t tot;
+  uint32_t run = (uint32_t)block_exclusive_scan<256>((uint64_t)sum, wsum, &tot);
   for (uint64_t c = c0; c < c1; c += COL_BATCH) {
     uint32_t v[COL_BATCH];
 #pragma unroll
@@ -2870,7 +2869,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   const unsigned col_chunks = (unsigned)((L.max_tiles + COL_CHUNK - 1) / COL_CHUNK);
   hipLaunchKernelGGL(k_col_reduce, dim3(col_chunks), dim3(256), 0, st, thist, csum,
                      &ctl->n_tiles, ctl, g0);
-  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, &ctl->n_tiles, ctl, g0);
+  hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, csum, &ctl->n_tiles, ctl, g0);
   hipLaunchKernelGGL(k_col_apply, dim3(col_chunks), dim3(256), 0, st, thist, csum,
                      &ctl->n_tiles, ctl, g0);
   hipLaunchKernelGGL(k_kept_keys, dim3(1), dim3(256), 0, st, thist, A.max_keys, ctl, g0);
@@ -2880,7 +2879,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   auto level_prefix = [&](const uint64_t *n_tiles_p, int gate) {
     hipLaunchKernelGGL(k_col_reduce, dim3(lcol_chunks), dim3(256), 0, st, thist, csum, n_tiles_p,
                        ctl, gate);
-    hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, st, csum, n_tiles_p, ctl, gate);
+    hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, csum, n_tiles_p, ctl, gate);
     hipLaunchKernelGGL(k_col_apply, dim3(lcol_chunks), dim3(256), 0, st, thist, csum, n_tiles_p,
                        ctl, gate);
   };
