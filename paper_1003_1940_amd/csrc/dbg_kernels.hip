@@ -2902,7 +2902,12 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
               kw0, kw1, key_words, thist};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
-  const unsigned level_grid = (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, 8192));
+  // persistent level grids: with 128-bit keys (two workgroups per CU) 2,048
+  // workgroups measured faster than 8,192 (40M-read k = 63 build: levels 2.3%
+  // faster, mostly the empty deep levels' launches); with 64-bit keys 8,192 stay
+  // faster
+  const unsigned level_grid =
+      (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, sizeof(K) == 16 ? 2048 : 8192));
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
   LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], &ctl->level_scatter_tiles[0],
                 hist[0], thist, cursor, wt0, wt1, titem, thist, bits, 0, 1};
