@@ -2902,12 +2902,15 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
               kw0, kw1, key_words, thist};
   hipLaunchKernelGGL(k_set_plan, dim3(grid_for(S, 1, 4096)), dim3(STREAM_NT), 0, st, pa, thist,
                      set_tbase, cursor0, set_kbase, S);
-  // persistent level grids: with 128-bit keys (two workgroups per CU) 2,048
-  // workgroups measured faster than 8,192 (40M-read k = 63 build: levels 2.3%
-  // faster, mostly the empty deep levels' launches); with 64-bit keys 8,192 stay
-  // faster
+  // persistent level grids.  With 128-bit keys the scatter holds two workgroups
+  // per CU, and a grid of just that many (512) measured fastest: each XCD's
+  // workgroups then work on one window of neighbouring tiles, whose runs of a
+  // digit meet in its L2 (40M-read k = 63 build at quarter size: levels 16.05
+  // ms per table at 8,192 workgroups, 15.68 at 2,048, 15.33 at 512); the in-tile
+  // pass is indifferent.  With 64-bit keys 8,192 measured faster than 2,048.
   const unsigned level_grid =
-      (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, sizeof(K) == 16 ? 2048 : 8192));
+      (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, sizeof(K) == 16 ? 512 : 8192));
+  const unsigned tiles_grid = (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, 8192));
   // endpoint route: the records are one bucket at level 0 (list 0 -> list 1)
   LevelArgs la0{items[0], &ctl->items[0], &ctl->level_tiles[0], &ctl->level_scatter_tiles[0],
                 hist[0], thist, cursor, wt0, wt1, titem, thist, bits, 0, 1};
@@ -2956,7 +2959,7 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
                  bits, lev, -1};
     hipLaunchKernelGGL(k_level_hist<K>, dim3(level_grid), dim3(STREAM_NT), 0, st, la, x0, x1, ctl);
     if (lev == seg_level)
-      hipLaunchKernelGGL(k_level_tiles<K>, dim3(level_grid), dim3(tiles_nt<K>()), 0, st, la, x0,
+      hipLaunchKernelGGL(k_level_tiles<K>, dim3(tiles_grid), dim3(tiles_nt<K>()), 0, st, la, x0,
                          x1, ctl);
     PlanArgs pl{items[li ^ 1], &ctl->items[li ^ 1], hist[li ^ 1], L.item_cap, batches,
                 L.batch_cap, uniform, L.item_cap, ctl, cap_u, bits, g0,
