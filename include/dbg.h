@@ -154,10 +154,11 @@ int dbg_build(const uint64_t *packed, uint64_t n_bases, const uint64_t *read_off
  * on every device it runs on until the process ends; the caller still passes
  * the inputs, the output tables and the result record.  A build that needs more
  * workspace than that (dbg_workspace_bytes(n_reads, 1, max_keys, k) above
- * DBG_NOALLOC_SCRATCH_BYTES: about 3.3 M k-mer positions for k <= 31 and 1.7 M
- * for k >= 33) returns DBG_E_SCRATCH and enqueues nothing.  Every call on a
- * device shares that device's array and leaves its contents behind (each build
- * initialises what it reads): calls in stream order on one stream are safe,
+ * DBG_NOALLOC_SCRATCH_BYTES: about 2.8 M k-mer positions for k <= 31 and 1.6 M
+ * for k >= 33, with reads of 100-150 bases) returns DBG_E_SCRATCH and enqueues
+ * nothing.  Every call on a device shares that device's array and leaves its
+ * contents behind (each build initialises what it reads): calls in stream
+ * order on one stream are safe,
  * calls that overlap on one device (other streams, other threads) race and
  * must not be issued.  The first call on a device looks up the array's address
  * there (DBG_E_HIP if that fails); nothing is allocated or freed.  Other errors
