@@ -720,12 +720,14 @@ __global__ __launch_bounds__(STREAM_NT) void k_enum_hist(EnumArgs a, uint32_t *t
         atomicAdd(&h[head_digit(heads[r], a.len)], 1u);
     }
   } else {
-    K keys[STREAM_KPT];
-    const int n = enum_keys<K, STREAM_KPT>(a, ts, g0, tr.end, tr.read_lo, tr.read_hi, keys);
-#pragma unroll
-    for (int r = 0; r < STREAM_KPT; ++r)
-      if (r < n && (!SL || in_slice(a, keys[r])))
-        atomicAdd(&h[msd_digit(keys[r], a.bits, 0)], 1u);
+    // one key at a time (waves with short reads, tiles beyond the LDS staging):
+    // the heads path above sets the kernel's registers
+    for (int r = 0; r < STREAM_KPT; ++r) {
+      K key[1];
+      if (enum_keys<K, 1>(a, ts, g0 + r, tr.end, tr.read_lo, tr.read_hi, key) &&
+          (!SL || in_slice(a, key[0])))
+        atomicAdd(&h[msd_digit(key[0], a.bits, 0)], 1u);
+    }
   }
   __syncthreads();
   thist[t * 256 + threadIdx.x] = h[threadIdx.x];
@@ -767,12 +769,12 @@ __global__ __launch_bounds__(STREAM_NT) void k_prefix_hist(EnumArgs a, uint64_t 
 #pragma unroll
       for (int r = 0; r < STREAM_KPT; ++r)
         if (r < nh) atomicAdd(&h[head_prefix(heads[r], a.len)], 1u);
-    } else {
-      K keys[STREAM_KPT];
-      const int n = enum_keys<K, STREAM_KPT>(a, ts, g0, tr.end, tr.read_lo, tr.read_hi, keys);
-#pragma unroll
-      for (int r = 0; r < STREAM_KPT; ++r)
-        if (r < n) atomicAdd(&h[key_prefix_bits(keys[r], a.bits)], 1u);
+    } else {  // one key at a time, as in k_enum_hist
+      for (int r = 0; r < STREAM_KPT; ++r) {
+        K key[1];
+        if (enum_keys<K, 1>(a, ts, g0 + r, tr.end, tr.read_lo, tr.read_hi, key))
+          atomicAdd(&h[key_prefix_bits(key[0], a.bits)], 1u);
+      }
     }
   }
   __syncthreads();
@@ -1382,6 +1384,9 @@ __global__ __launch_bounds__(STREAM_NT) void k_level_plan(PlanArgs p, LevelArgs 
     if (it.in_tile) {  // the sum over the bucket's tiles of digit d's segment
       const SegParent sp{it.tbase, (uint32_t)((it.size + TILE - 1) / TILE), (uint32_t)it.size};
       const uint32_t d = threadIdx.x;
+      // the rows of all the bucket's tiles are independent loads: unrolled, they
+      // are in flight together instead of one tile's round trip at a time
+#pragma unroll 8
       for (uint32_t i = 0; i < sp.tiles; ++i) c += seg_row(p, sp, i, d + 1) - seg_row(p, sp, i, d);
       plan_children(p, c, it.off, 1u, a.level + 1, nullptr, lds, &sp);
       continue;
