@@ -2911,8 +2911,9 @@ static hipError_t run_table(const BuildArgs &A, const Layout &L, bool edges) {
   // per CU, and a grid of just that many (512) measured fastest: each XCD's
   // workgroups then work on one window of neighbouring tiles, whose runs of a
   // digit meet in its L2 (40M-read k = 63 build at quarter size: levels 16.05
-  // ms per table at 8,192 workgroups, 15.68 at 2,048, 15.33 at 512); the in-tile
-  // pass is indifferent.  With 64-bit keys 8,192 measured faster than 2,048.
+  // ms per table at 8,192 workgroups, 15.68 at 2,048, 15.33 at 512, 16.8 at 256,
+  // which leaves half the CU's slots empty); the in-tile pass is indifferent.
+  // With 64-bit keys 8,192 measured faster than 2,048 and 1,024.
   const unsigned level_grid =
       (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, sizeof(K) == 16 ? 512 : 8192));
   const unsigned tiles_grid = (unsigned)xcd_grid(grid_for(L.max_tiles + L.item_cap, 1, 8192));
